@@ -1,0 +1,269 @@
+/*
+ * CPU oracle for the batched Kronecker-product action (Jhurani, "Batched
+ * Kronecker product for 2-D matrices and 3-D arrays on NVIDIA GPUs").
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow, obviously correct
+ * reference that the HIP library is checked against.  Only the test suite,
+ * the smoke check and the CPU-baseline leg of the benchmark may load it.  It
+ * shares no code, header or constant with the GPU library.
+ *
+ * Storage (Section 3, "Batched function interface"): every matrix and every
+ * operand is column-major with the smallest leading dimensions, and operand p
+ * starts at p*n^2 (2-D) or p*n^3 (3-D) elements, as in the measured setting of
+ * Section 5.
+ *
+ * 2-D (Section 2, the defining identity (A (x) B) vec(X) = vec(B X A^T)):
+ *     X_p is n x n, element (l, m) at l + n*m, and Y_p = B * X_p * A^T.
+ *     Computed as T = B * X_p (sum over l ascending), then Y_p = T * A^T
+ *     (sum over m ascending): 4 n^3 flops per operand (Section 5 flop model).
+ *
+ * 3-D (Section 2.1, the triple summation and vec(Y) = (C (x) B (x) A) vec(X)):
+ *     the paper's operator K(P, Q, R) applies P to the fastest (first,
+ *     column-major) index, Q to the middle one and R to the slowest:
+ *         Y_ijk = sum_{l,m,n} P_il Q_jm R_kn X_lmn,  X_lmn at l + n*m + n^2*n'.
+ *     The library's kron3d(A, B, C) is vec(Y) = (A (x) B (x) C) vec(X) on the
+ *     memory-order vector, which is the paper's K(C, B, A): C contracts the
+ *     fastest index, B the middle one, A the slowest.  Three mode products
+ *     in the fixed order fastest, middle, slowest: 6 n^4 flops per operand.
+ *
+ * Gradients of L = sum_p <dY_p, Y_p> (inner product of the flattened arrays)
+ * with respect to X_p and to the shared matrices, summed over the batch.
+ * They are written out from the summation forms above:
+ *   2-D: dX_p = B^T dY_p A;  dA = sum_p dY_p^T (B X_p);  dB = sum_p dY_p (X_p A^T)^T
+ *   3-D: dX = K(C^T, B^T, A^T) dY; dA/dB/dC contract dY with X after the two
+ *        other factors have been applied (see the functions below).
+ *
+ * The float variants keep storage and accumulation in float and must be built
+ * with -ffp-contract=off so that no multiply-add is fused.
+ */
+#include <stddef.h>
+#include <stdint.h>
+#include <string.h>
+#include <stdlib.h>
+
+#define ORACLE_API __attribute__((visibility("default")))
+
+/* ---- generic bodies, instantiated for double and float ---------------- */
+
+/* Y_p = B X_p A^T, column-major n x n, for p in [0, batch). */
+#define DEFINE_KRON2D(NAME, T)                                                   \
+  ORACLE_API void NAME(int n, const T* A, const T* B, const T* X, T* Y,          \
+                       int64_t batch) {                                         \
+    const int64_t nn = (int64_t)n * n;                                           \
+    _Pragma("omp parallel for schedule(static)")                                 \
+    for (int64_t p = 0; p < batch; ++p) {                                        \
+      T tmp[16 * 16];                                                            \
+      const T* x = X + p * nn;                                                   \
+      T* y = Y + p * nn;                                                         \
+      /* T = B * X: T(r, m) = sum_l B(r, l) X(l, m) */                           \
+      for (int m = 0; m < n; ++m)                                                \
+        for (int r = 0; r < n; ++r) {                                            \
+          T s = 0;                                                               \
+          for (int l = 0; l < n; ++l) s += B[r + n * l] * x[l + n * m];          \
+          tmp[r + n * m] = s;                                                    \
+        }                                                                        \
+      /* Y = T * A^T: Y(r, c) = sum_m T(r, m) A(c, m) */                         \
+      for (int c = 0; c < n; ++c)                                                \
+        for (int r = 0; r < n; ++r) {                                            \
+          T s = 0;                                                               \
+          for (int m = 0; m < n; ++m) s += tmp[r + n * m] * A[c + n * m];        \
+          y[r + n * c] = s;                                                      \
+        }                                                                        \
+    }                                                                            \
+  }
+
+/* Paper's K(P, Q, R) on column-major n x n x n arrays:
+ *   Y(i,j,k) = sum_{l,m,q} P(i,l) Q(j,m) R(k,q) X(l,m,q),
+ *   element (l, m, q) at l + n*m + n*n*q.
+ * Done as three mode products: first index (P), then second (Q), then third (R). */
+#define DEFINE_KPQR(NAME, T)                                                     \
+  static void NAME(int n, const T* P, const T* Q, const T* R, const T* x,        \
+                   T* y, T* w1, T* w2) {                                         \
+    const int nn = n * n;                                                        \
+    /* w1(i, m, q) = sum_l P(i, l) x(l, m, q) */                                 \
+    for (int q = 0; q < n; ++q)                                                  \
+      for (int m = 0; m < n; ++m)                                                \
+        for (int i = 0; i < n; ++i) {                                            \
+          T s = 0;                                                               \
+          for (int l = 0; l < n; ++l) s += P[i + n * l] * x[l + n * m + nn * q]; \
+          w1[i + n * m + nn * q] = s;                                            \
+        }                                                                        \
+    /* w2(i, j, q) = sum_m Q(j, m) w1(i, m, q) */                                \
+    for (int q = 0; q < n; ++q)                                                  \
+      for (int j = 0; j < n; ++j)                                                \
+        for (int i = 0; i < n; ++i) {                                            \
+          T s = 0;                                                               \
+          for (int m = 0; m < n; ++m) s += Q[j + n * m] * w1[i + n * m + nn * q];\
+          w2[i + n * j + nn * q] = s;                                            \
+        }                                                                        \
+    /* y(i, j, k) = sum_q R(k, q) w2(i, j, q) */                                 \
+    for (int k = 0; k < n; ++k)                                                  \
+      for (int j = 0; j < n; ++j)                                                \
+        for (int i = 0; i < n; ++i) {                                            \
+          T s = 0;                                                               \
+          for (int q = 0; q < n; ++q) s += R[k + n * q] * w2[i + n * j + nn * q];\
+          y[i + n * j + nn * k] = s;                                             \
+        }                                                                        \
+  }
+
+/* vec(Y_p) = (A (x) B (x) C) vec(X_p) = paper's K(C, B, A)(X_p). */
+#define DEFINE_KRON3D(NAME, KPQR, T)                                             \
+  ORACLE_API void NAME(int n, const T* A, const T* B, const T* C, const T* X,    \
+                       T* Y, int64_t batch) {                                    \
+    const int64_t nnn = (int64_t)n * n * n;                                      \
+    _Pragma("omp parallel for schedule(static)")                                 \
+    for (int64_t p = 0; p < batch; ++p) {                                        \
+      T w1[16 * 16 * 16], w2[16 * 16 * 16];                                      \
+      KPQR(n, C, B, A, X + p * nnn, Y + p * nnn, w1, w2);                        \
+    }                                                                            \
+  }
+
+DEFINE_KRON2D(oracle_kron2d_f64, double)
+DEFINE_KRON2D(oracle_kron2d_f32, float)
+DEFINE_KPQR(kpqr_f64, double)
+DEFINE_KPQR(kpqr_f32, float)
+DEFINE_KRON3D(oracle_kron3d_f64, kpqr_f64, double)
+DEFINE_KRON3D(oracle_kron3d_f32, kpqr_f32, float)
+
+/* ---- gradients (double only) ------------------------------------------ */
+
+static void transpose_n(int n, const double* M, double* Mt) {
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) Mt[j + n * i] = M[i + n * j];
+}
+
+static double* zalloc(size_t count) { return (double*)calloc(count ? count : 1, sizeof(double)); }
+
+/* 2-D: Y_p = B X_p A^T with L = sum_p <dY_p, Y_p>.
+ *   dX_p = B^T dY_p A                                 (the adjoint action)
+ *   dA(c, m) = sum_p sum_r dY_p(r, c) (B X_p)(r, m)   (dA = sum_p dY_p^T B X_p)
+ *   dB(r, l) = sum_p sum_c dY_p(r, c) (X_p A^T)(l, c) (dB = sum_p dY_p A X_p^T)
+ * Any output pointer may be NULL to skip it.  dA/dB are overwritten. */
+ORACLE_API void oracle_kron2d_grad_f64(int n, const double* A, const double* B,
+                                       const double* X, const double* dY,
+                                       double* dX, double* dA, double* dB,
+                                       int64_t batch) {
+  const int64_t nn = (int64_t)n * n;
+  if (dX) {
+    double At[256], Bt[256];
+    transpose_n(n, A, At);
+    transpose_n(n, B, Bt);
+    /* B^T dY A = Bt dY (At)^T, i.e. the forward action with (At, Bt). */
+    oracle_kron2d_f64(n, At, Bt, dY, dX, batch);
+  }
+  if (dA) memset(dA, 0, sizeof(double) * nn);
+  if (dB) memset(dB, 0, sizeof(double) * nn);
+  if (!dA && !dB) return;
+  for (int64_t p = 0; p < batch; ++p) {
+    const double* x = X + p * nn;
+    const double* dy = dY + p * nn;
+    if (dA) {
+      double bx[256];
+      for (int m = 0; m < n; ++m)
+        for (int r = 0; r < n; ++r) {
+          double s = 0;
+          for (int l = 0; l < n; ++l) s += B[r + n * l] * x[l + n * m];
+          bx[r + n * m] = s;
+        }
+      for (int m = 0; m < n; ++m)
+        for (int c = 0; c < n; ++c) {
+          double s = 0;
+          for (int r = 0; r < n; ++r) s += dy[r + n * c] * bx[r + n * m];
+          dA[c + n * m] += s;
+        }
+    }
+    if (dB) {
+      double xa[256]; /* xa(l, c) = sum_m X(l, m) A(c, m) */
+      for (int c = 0; c < n; ++c)
+        for (int l = 0; l < n; ++l) {
+          double s = 0;
+          for (int m = 0; m < n; ++m) s += x[l + n * m] * A[c + n * m];
+          xa[l + n * c] = s;
+        }
+      for (int l = 0; l < n; ++l)
+        for (int r = 0; r < n; ++r) {
+          double s = 0;
+          for (int c = 0; c < n; ++c) s += dy[r + n * c] * xa[l + n * c];
+          dB[r + n * l] += s;
+        }
+    }
+  }
+}
+
+/* 3-D: memory index of operand element (a, b, c) is a*n^2 + b*n + c, and
+ *   Y(i, j, k) = sum_{a,b,c} A(i, a) B(j, b) C(k, c) X(a, b, c),
+ * with matrices column-major (A(i, a) at i + n*a).  With L = sum_p <dY_p, Y_p>:
+ *   dX(a, b, c) = sum_{i,j,k} A(i, a) B(j, b) C(k, c) dY(i, j, k)
+ *   dA(i, a) = sum_p sum_{j,k} dY(i, j, k) U(a, j, k),  U = X with B on b, C on c
+ *   dB(j, b) = sum_p sum_{i,k} dY(i, j, k) V(i, b, k),  V = X with A on a, C on c
+ *   dC(k, c) = sum_p sum_{i,j} dY(i, j, k) W(i, j, c),  W = X with A on a, B on b
+ * The partial products U, V, W are formed with the same K(P, Q, R) helper by
+ * passing the identity for the factor that is left out.  dA/dB/dC are
+ * overwritten; any output may be NULL. */
+ORACLE_API void oracle_kron3d_grad_f64(int n, const double* A, const double* B,
+                                       const double* C, const double* X,
+                                       const double* dY, double* dX, double* dA,
+                                       double* dB, double* dC, int64_t batch) {
+  const int64_t nn = (int64_t)n * n, nnn = nn * n;
+  double At[256], Bt[256], Ct[256], I[256];
+  transpose_n(n, A, At);
+  transpose_n(n, B, Bt);
+  transpose_n(n, C, Ct);
+  for (int i = 0; i < n * n; ++i) I[i] = 0.0;
+  for (int i = 0; i < n; ++i) I[i + n * i] = 1.0;
+  if (dX) oracle_kron3d_f64(n, At, Bt, Ct, dY, dX, batch);
+  if (dA) memset(dA, 0, sizeof(double) * nn);
+  if (dB) memset(dB, 0, sizeof(double) * nn);
+  if (dC) memset(dC, 0, sizeof(double) * nn);
+  if (!dA && !dB && !dC) return;
+  double* u = zalloc(nnn);
+  double* w1 = zalloc(nnn);
+  double* w2 = zalloc(nnn);
+  for (int64_t p = 0; p < batch; ++p) {
+    const double* x = X + p * nnn;
+    const double* dy = dY + p * nnn;
+    if (dA) { /* U = K(C, B, I) x: C on the fastest index c, B on b, a untouched */
+      kpqr_f64(n, C, B, I, x, u, w1, w2);
+      for (int i = 0; i < n; ++i)
+        for (int a = 0; a < n; ++a) {
+          double s = 0;
+          for (int j = 0; j < n; ++j)
+            for (int k = 0; k < n; ++k) s += dy[i * nn + j * n + k] * u[a * nn + j * n + k];
+          dA[i + n * a] += s;
+        }
+    }
+    if (dB) { /* V = K(C, I, A) x */
+      kpqr_f64(n, C, I, A, x, u, w1, w2);
+      for (int j = 0; j < n; ++j)
+        for (int b = 0; b < n; ++b) {
+          double s = 0;
+          for (int i = 0; i < n; ++i)
+            for (int k = 0; k < n; ++k) s += dy[i * nn + j * n + k] * u[i * nn + b * n + k];
+          dB[j + n * b] += s;
+        }
+    }
+    if (dC) { /* W = K(I, B, A) x */
+      kpqr_f64(n, I, B, A, x, u, w1, w2);
+      for (int k = 0; k < n; ++k)
+        for (int c = 0; c < n; ++c) {
+          double s = 0;
+          for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) s += dy[i * nn + j * n + k] * u[i * nn + j * n + c];
+          dC[k + n * c] += s;
+        }
+    }
+  }
+  free(u);
+  free(w1);
+  free(w2);
+}
+
+/* Number of OpenMP threads the oracle would use (for reporting). */
+ORACLE_API int oracle_num_threads(void) {
+  int t = 1;
+#ifdef _OPENMP
+  extern int omp_get_max_threads(void);
+  t = omp_get_max_threads();
+#endif
+  return t;
+}

@@ -1,0 +1,380 @@
+"""Pins of the CPU oracle to facts fixed by the paper and by mathematics.
+
+Each ``pin_*`` function takes an oracle object (``oracle.Oracle``) and raises
+AssertionError when the oracle disagrees with a value that does not come from
+the oracle's own arithmetic: a hand-derived worked example, an explicitly
+formed Kronecker matrix (numpy.kron), an algebraic identity, a closed form, a
+reduction to a numpy library routine, the paper's Algorithm 1 restated in
+numpy, or central finite differences.  The same functions are run against
+deliberately altered builds of the oracle to show that they catch mistakes.
+
+Conventions (shared with the oracle): matrices are column-major flat arrays;
+2-D operands are column-major n x n blocks with Y_p = B X_p A^T; 3-D operands
+hold element (a, b, c) at a*n^2 + b*n + c and vec(Y) = (A kron B kron C) vec(X).
+"""
+import os
+
+import numpy as np
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+# ---- small helpers (no Kronecker arithmetic here) ---------------------------
+
+def cm(M):
+    """Math matrix -> column-major flat array."""
+    return np.asarray(M).reshape(-1, order="F")
+
+
+def mat(flat, n):
+    """Column-major flat array -> math matrix."""
+    return np.asarray(flat).reshape(n, n, order="F")
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    d = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (d if d > 0 else 1.0)
+
+
+def read_golden(name):
+    vals = {}
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            key, *rest = line.split()
+            vals[key] = np.array([float(v) for v in rest])
+    return vals
+
+
+def rand_mats(rng, n, k):
+    return [rng.uniform(-1, 1, n * n) for _ in range(k)]
+
+
+# ---- P0: hand-derived worked examples (golden fixtures) --------------------
+
+def pin_worked_examples(orc):
+    g = read_golden("worked_2d_n2.txt")
+    n = int(g["n"][0])
+    for prec in ("f64", "f32"):
+        y = orc.kron2d(n, g["A"], g["B"], g["X"], 1, prec)
+        assert np.array_equal(y.astype(np.float64), g["Y"]), ("worked 2-D", prec, y)
+    g = read_golden("worked_3d_n2.txt")
+    n = int(g["n"][0])
+    for prec in ("f64", "f32"):
+        y = orc.kron3d(n, g["A"], g["B"], g["C"], g["X"], 1, prec)
+        assert np.array_equal(y.astype(np.float64), g["Y"]), ("worked 3-D", prec, y)
+
+
+# ---- P1: brute force with the explicitly formed Kronecker matrix ------------
+
+def pin_brute_force(orc, seed=1):
+    rng = np.random.default_rng(seed)
+    for n in range(1, 9):
+        A, B = rand_mats(rng, n, 2)
+        batch = 3
+        X = rng.standard_normal(batch * n * n)
+        K = np.kron(mat(A, n), mat(B, n))
+        want = (X.reshape(batch, n * n) @ K.T).reshape(-1)
+        got = orc.kron2d(n, A, B, X, batch, "f64")
+        assert rel(got, want) < 1e-14, ("2-D brute force", n, rel(got, want))
+        got32 = orc.kron2d(n, A, B, X, batch, "f32")
+        assert rel(got32, want) < 2e-6, ("2-D brute force f32", n, rel(got32, want))
+    for n in range(1, 6):
+        A, B, C = rand_mats(rng, n, 3)
+        batch = 2
+        X = rng.standard_normal(batch * n ** 3)
+        K = np.kron(mat(A, n), np.kron(mat(B, n), mat(C, n)))
+        want = (X.reshape(batch, n ** 3) @ K.T).reshape(-1)
+        got = orc.kron3d(n, A, B, C, X, batch, "f64")
+        assert rel(got, want) < 1e-14, ("3-D brute force", n, rel(got, want))
+        got32 = orc.kron3d(n, A, B, C, X, batch, "f32")
+        assert rel(got32, want) < 3e-6, ("3-D brute force f32", n, rel(got32, want))
+
+
+# ---- P2: identity factors reproduce X bit for bit ----------------------------
+
+def pin_identity(orc, seed=2):
+    rng = np.random.default_rng(seed)
+    for n in (1, 3, 7, 16):
+        I = cm(np.eye(n))
+        X = rng.standard_normal(5 * n * n)
+        for prec in ("f64", "f32"):
+            y = orc.kron2d(n, I, I, X, 5, prec)
+            assert np.array_equal(y, X.astype(y.dtype)), ("identity 2-D", n, prec)
+        X3 = rng.standard_normal(2 * n ** 3)
+        for prec in ("f64", "f32"):
+            y = orc.kron3d(n, I, I, I, X3, 2, prec)
+            assert np.array_equal(y, X3.astype(y.dtype)), ("identity 3-D", n, prec)
+
+
+# ---- P3: permutation factors move entries exactly ----------------------------
+
+def perm_cm(n, perm):
+    P = np.zeros((n, n))
+    P[np.arange(n), perm] = 1.0
+    return cm(P)
+
+
+def pin_permutation(orc, seed=3):
+    """With P[i, perm[i]] = 1 the action is a pure gather, computed here with
+    numpy indexing: 2-D Y[p, i, j] = X[p, pa[i], pb[j]] in the (slow, fast)
+    memory view; 3-D Y[p, i, j, k] = X[p, pa[i], pb[j], pc[k]]."""
+    rng = np.random.default_rng(seed)
+    for n in (2, 5, 8, 13, 16):
+        pa, pb, pc = (rng.permutation(n) for _ in range(3))
+        batch = 3
+        X = np.arange(batch * n * n, dtype=np.float64) + 1.0
+        want = X.reshape(batch, n, n)[:, pa][:, :, pb].reshape(-1)
+        for prec in ("f64", "f32"):
+            y = orc.kron2d(n, perm_cm(n, pa), perm_cm(n, pb), X, batch, prec)
+            assert np.array_equal(y.astype(np.float64), want), ("perm 2-D", n, prec)
+        X3 = np.arange(batch * n ** 3, dtype=np.float64) + 1.0
+        want3 = X3.reshape(batch, n, n, n)[:, pa][:, :, pb][:, :, :, pc].reshape(-1)
+        for prec in ("f64", "f32"):
+            y = orc.kron3d(n, perm_cm(n, pa), perm_cm(n, pb), perm_cm(n, pc), X3, batch, prec)
+            assert np.array_equal(y.astype(np.float64), want3), ("perm 3-D", n, prec)
+
+
+# ---- P4: small integers, where every partial sum is exact -------------------
+
+def pin_small_integers(orc, seed=4):
+    """Entries of A, B, C in {-2..2} and of X in {-8..8}: every partial sum is an
+    integer below 2^24, so float and double results must both equal the exact
+    integer result of the explicitly formed (integer) Kronecker matrix."""
+    rng = np.random.default_rng(seed)
+    for n in (3, 8, 16):
+        A, B, C = (rng.integers(-2, 3, n * n) for _ in range(3))
+        batch = 2
+        X = rng.integers(-8, 9, batch * n * n)
+        K = np.kron(mat(A, n), mat(B, n)).astype(np.int64)
+        want = (X.reshape(batch, -1).astype(np.int64) @ K.T).reshape(-1)
+        for prec in ("f64", "f32"):
+            y = orc.kron2d(n, A, B, X, batch, prec)
+            assert np.array_equal(y.astype(np.int64), want) and np.all(y == want), ("ints 2-D", n, prec)
+        if n <= 8:
+            X3 = rng.integers(-8, 9, batch * n ** 3)
+            K3 = np.kron(mat(A, n), np.kron(mat(B, n), mat(C, n))).astype(np.int64)
+            want3 = (X3.reshape(batch, -1).astype(np.int64) @ K3.T).reshape(-1)
+            for prec in ("f64", "f32"):
+                y = orc.kron3d(n, A, B, C, X3, batch, prec)
+                assert np.all(y == want3), ("ints 3-D", n, prec)
+
+
+# ---- P5: mixed-product rule -------------------------------------------------
+
+def pin_mixed_product(orc, seed=5):
+    """(A1 kron B1)(A2 kron B2) = (A1 A2) kron (B1 B2): applying two actions in
+    a row equals one action with the products of the factors."""
+    rng = np.random.default_rng(seed)
+    for n in (4, 11, 16):
+        A1, B1, C1, A2, B2, C2 = rand_mats(rng, n, 6)
+        M = lambda P, Q: cm(mat(P, n) @ mat(Q, n))
+        X = rng.standard_normal(4 * n * n)
+        two = orc.kron2d(n, A1, B1, orc.kron2d(n, A2, B2, X, 4), 4)
+        one = orc.kron2d(n, M(A1, A2), M(B1, B2), X, 4)
+        assert rel(two, one) < 1e-13, ("mixed product 2-D", n)
+        X3 = rng.standard_normal(2 * n ** 3)
+        two = orc.kron3d(n, A1, B1, C1, orc.kron3d(n, A2, B2, C2, X3, 2), 2)
+        one = orc.kron3d(n, M(A1, A2), M(B1, B2), M(C1, C2), X3, 2)
+        assert rel(two, one) < 1e-13, ("mixed product 3-D", n)
+
+
+# ---- P6: adjoint identity --------------------------------------------------
+
+def pin_adjoint(orc, seed=6):
+    """<K(A,B) X, Z> = <X, K(A^T, B^T) Z>, since (A kron B)^T = A^T kron B^T."""
+    rng = np.random.default_rng(seed)
+    T = lambda P, n: cm(mat(P, n).T)
+    for n in (3, 10, 16):
+        A, B, C = rand_mats(rng, n, 3)
+        X, Z = rng.standard_normal(3 * n * n), rng.standard_normal(3 * n * n)
+        lhs = np.dot(orc.kron2d(n, A, B, X, 3), Z)
+        rhs = np.dot(X, orc.kron2d(n, T(A, n), T(B, n), Z, 3))
+        assert abs(lhs - rhs) <= 1e-12 * (abs(lhs) + 1), ("adjoint 2-D", n)
+        X, Z = rng.standard_normal(2 * n ** 3), rng.standard_normal(2 * n ** 3)
+        lhs = np.dot(orc.kron3d(n, A, B, C, X, 2), Z)
+        rhs = np.dot(X, orc.kron3d(n, T(A, n), T(B, n), T(C, n), Z, 2))
+        assert abs(lhs - rhs) <= 1e-12 * (abs(lhs) + 1), ("adjoint 3-D", n)
+
+
+# ---- P7: one non-identity factor reduces to a plain matrix product ----------
+
+def pin_single_factor(orc, seed=7):
+    rng = np.random.default_rng(seed)
+    for n in (2, 9, 16):
+        I = cm(np.eye(n))
+        M = rng.uniform(-1, 1, n * n)
+        Mm = mat(M, n)
+        batch = 4
+        X = rng.standard_normal(batch * n * n)
+        Xm = X.reshape(batch, n, n).transpose(0, 2, 1)   # column-major operands
+        # K(I, B) X = B X  and  K(A, I) X = X A^T
+        got = orc.kron2d(n, I, M, X, batch).reshape(batch, n, n).transpose(0, 2, 1)
+        assert rel(got, np.matmul(Mm, Xm)) < 1e-14, ("B only", n)
+        got = orc.kron2d(n, M, I, X, batch).reshape(batch, n, n).transpose(0, 2, 1)
+        assert rel(got, np.matmul(Xm, Mm.T)) < 1e-14, ("A only", n)
+        X3 = rng.standard_normal(2 * n ** 3).reshape(2, n, n, n)
+        # each factor alone acts along its own memory axis (A slowest, C fastest)
+        got = orc.kron3d(n, M, I, I, X3, 2).reshape(2, n, n, n)
+        assert rel(got, np.einsum("ia,pabc->pibc", Mm, X3)) < 1e-14, ("A only 3-D", n)
+        got = orc.kron3d(n, I, M, I, X3, 2).reshape(2, n, n, n)
+        assert rel(got, np.einsum("jb,pabc->pajc", Mm, X3)) < 1e-14, ("B only 3-D", n)
+        got = orc.kron3d(n, I, I, M, X3, 2).reshape(2, n, n, n)
+        assert rel(got, np.matmul(X3, Mm.T)) < 1e-14, ("C only 3-D", n)
+
+
+# ---- P8: rank-one operands have a closed form ------------------------------
+
+def pin_rank_one(orc, seed=8):
+    """X = u kron v (kron w) in memory order maps to (A u) kron (B v) (kron (C w))."""
+    rng = np.random.default_rng(seed)
+    for n in (1, 6, 16):
+        A, B, C = rand_mats(rng, n, 3)
+        u, v, w = (rng.standard_normal(n) for _ in range(3))
+        X = np.kron(u, v)
+        want = np.kron(mat(A, n) @ u, mat(B, n) @ v)
+        assert rel(orc.kron2d(n, A, B, X, 1), want) < 1e-14, ("rank-1 2-D", n)
+        X3 = np.kron(u, np.kron(v, w))
+        want3 = np.kron(mat(A, n) @ u, np.kron(mat(B, n) @ v, mat(C, n) @ w))
+        assert rel(orc.kron3d(n, A, B, C, X3, 1), want3) < 1e-14, ("rank-1 3-D", n)
+
+
+# ---- P9: the paper's Algorithm 1 as an independent 3-D formulation ---------
+
+def algorithm1(P, Q, R, X):
+    """Algorithm 1 of Section 4 restated with numpy on one column-major array X
+    of shape (na, nb, nc): first every slice X(:,:,N) becomes P X(:,:,N) Q^T in
+    tmp, then for every J the matrix tmp(:,J,:) is multiplied by R^T on the
+    right and stored as Y(:,J,:).  Returns Y with vec(Y) = (R kron Q kron P) vec(X)."""
+    ma, mb, mc = P.shape[0], Q.shape[0], R.shape[0]
+    nc = X.shape[2]
+    tmp = np.zeros((ma, mb, nc))
+    for N in range(nc):
+        tmp[:, :, N] = P @ X[:, :, N] @ Q.T
+    Y = np.zeros((ma, mb, mc))
+    for J in range(mb):
+        Y[:, J, :] = tmp[:, J, :] @ R.T
+    return Y
+
+
+def pin_algorithm1(orc, seed=9):
+    rng = np.random.default_rng(seed)
+    for n in (2, 5, 10, 16):
+        A, B, C = rand_mats(rng, n, 3)
+        Xflat = rng.standard_normal(n ** 3)
+        # memory index a*n^2 + b*n + c is the column-major index of (c, b, a)
+        Xcm = Xflat.reshape(n, n, n, order="C").transpose(2, 1, 0)   # Xcm[c, b, a]
+        Ycm = algorithm1(mat(C, n), mat(B, n), mat(A, n), Xcm)
+        want = Ycm.transpose(2, 1, 0).reshape(-1)
+        got = orc.kron3d(n, A, B, C, Xflat, 1)
+        assert rel(got, want) < 1e-14, ("Algorithm 1", n, rel(got, want))
+
+
+# ---- P10: linearity ---------------------------------------------------------
+
+def pin_linearity(orc, seed=10):
+    rng = np.random.default_rng(seed)
+    n = 7
+    A, B, C, A2 = rand_mats(rng, n, 4)
+    X1, X2 = rng.standard_normal(2 * n ** 3), rng.standard_normal(2 * n ** 3)
+    a, b = 0.75, -2.5
+    lhs = orc.kron3d(n, A, B, C, a * X1 + b * X2, 2)
+    rhs = a * orc.kron3d(n, A, B, C, X1, 2) + b * orc.kron3d(n, A, B, C, X2, 2)
+    assert rel(lhs, rhs) < 1e-14, "linearity in X"
+    lhs = orc.kron3d(n, A + A2, B, C, X1, 2)
+    rhs = orc.kron3d(n, A, B, C, X1, 2) + orc.kron3d(n, A2, B, C, X1, 2)
+    assert rel(lhs, rhs) < 1e-14, "linearity in A"
+    lhs = orc.kron2d(n, A, 3.0 * B, X1[: 2 * n * n], 2)
+    rhs = 3.0 * orc.kron2d(n, A, B, X1[: 2 * n * n], 2)
+    assert rel(lhs, rhs) < 1e-14, "scaling in B"
+
+
+# ---- P11: batch independence ------------------------------------------------
+
+def pin_batch_independence(orc, seed=11):
+    rng = np.random.default_rng(seed)
+    for n in (4, 16):
+        A, B, C = rand_mats(rng, n, 3)
+        batch, q = 6, 3
+        X = rng.standard_normal(batch * n * n)
+        X[q * n * n + 5] = np.nan
+        Y = orc.kron2d(n, A, B, X, batch).reshape(batch, -1)
+        for p in range(batch):
+            assert np.all(np.isnan(Y[p])) if p == q else np.all(np.isfinite(Y[p])), ("NaN 2-D", n, p)
+        # each operand alone gives the same result as in the batch
+        single = orc.kron2d(n, A, B, X[: n * n], 1)
+        assert np.array_equal(single, Y[0]), ("batch 2-D", n)
+        X3 = rng.standard_normal(batch * n ** 3)
+        X3[q * n ** 3 + 7] = np.nan
+        Y3 = orc.kron3d(n, A, B, C, X3, batch).reshape(batch, -1)
+        for p in range(batch):
+            assert np.any(np.isnan(Y3[p])) if p == q else np.all(np.isfinite(Y3[p])), ("NaN 3-D", n, p)
+        single = orc.kron3d(n, A, B, C, X3[(batch - 1) * n ** 3:], 1)
+        assert np.array_equal(single, Y3[batch - 1]), ("batch 3-D", n)
+
+
+# ---- P12: gradients against central differences and the explicit matrix ----
+
+def _fd(f, x, h):
+    g = np.empty(x.size)
+    for i in range(x.size):
+        xp, xm = x.copy(), x.copy()
+        xp[i] += h
+        xm[i] -= h
+        g[i] = (f(xp) - f(xm)) / (2 * h)
+    return g
+
+
+def pin_gradients(orc, seed=12):
+    """L = sum_p <dY_p, Y_p> is linear in X and in each factor, so a central
+    difference with h = 1e-3 has no truncation error; dX is also checked
+    against the transposed explicit Kronecker matrix."""
+    rng = np.random.default_rng(seed)
+    h = 1e-3
+    for n in (1, 3, 5):
+        batch = 3
+        A, B = rand_mats(rng, n, 2)
+        X, dY = rng.standard_normal(batch * n * n), rng.standard_normal(batch * n * n)
+        dX, dA, dB = orc.kron2d_grad(n, A, B, X, dY, batch)
+        K = np.kron(mat(A, n), mat(B, n))
+        assert rel(dX, (dY.reshape(batch, -1) @ K).reshape(-1)) < 1e-13, ("dX 2-D", n)
+        L = lambda A_, B_, X_: float(np.dot(dY, orc.kron2d(n, A_, B_, X_, batch)))
+        assert rel(dA, _fd(lambda a: L(a, B, X), A, h)) < 1e-8, ("dA 2-D", n)
+        assert rel(dB, _fd(lambda b: L(A, b, X), B, h)) < 1e-8, ("dB 2-D", n)
+    for n in (1, 2, 4):
+        batch = 2
+        A, B, C = rand_mats(rng, n, 3)
+        X, dY = rng.standard_normal(batch * n ** 3), rng.standard_normal(batch * n ** 3)
+        dX, dA, dB, dC = orc.kron3d_grad(n, A, B, C, X, dY, batch)
+        K = np.kron(mat(A, n), np.kron(mat(B, n), mat(C, n)))
+        assert rel(dX, (dY.reshape(batch, -1) @ K).reshape(-1)) < 1e-13, ("dX 3-D", n)
+        L = lambda A_, B_, C_: float(np.dot(dY, orc.kron3d(n, A_, B_, C_, X, batch)))
+        assert rel(dA, _fd(lambda a: L(a, B, C), A, h)) < 1e-8, ("dA 3-D", n)
+        assert rel(dB, _fd(lambda b: L(A, b, C), B, h)) < 1e-8, ("dB 3-D", n)
+        assert rel(dC, _fd(lambda c: L(A, B, c), C, h)) < 1e-8, ("dC 3-D", n)
+
+
+# ---- FP32 variant tracks FP64 at float accuracy ----------------------------
+
+def pin_float_accuracy(orc, seed=13):
+    rng = np.random.default_rng(seed)
+    for n in (10, 16):
+        A, B, C = rand_mats(rng, n, 3)
+        X = rng.standard_normal(8 * n * n)
+        e = rel(orc.kron2d(n, A, B, X, 8, "f32"), orc.kron2d(n, A, B, X, 8, "f64"))
+        assert 0 < e < 1e-6, ("f32 2-D accuracy", n, e)
+        X3 = rng.standard_normal(2 * n ** 3)
+        e = rel(orc.kron3d(n, A, B, C, X3, 2, "f32"), orc.kron3d(n, A, B, C, X3, 2, "f64"))
+        assert 0 < e < 1e-6, ("f32 3-D accuracy", n, e)
+
+
+ALL_PINS = [
+    pin_worked_examples, pin_brute_force, pin_identity, pin_permutation,
+    pin_small_integers, pin_mixed_product, pin_adjoint, pin_single_factor,
+    pin_rank_one, pin_algorithm1, pin_linearity, pin_batch_independence,
+    pin_gradients, pin_float_accuracy,
+]
