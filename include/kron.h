@@ -1,0 +1,127 @@
+/*
+ * kron.h -- C ABI of the MI355X (gfx950) batched Kronecker-product action.
+ *
+ * Operation (Jhurani, "Batched Kronecker product for 2-D matrices and 3-D
+ * arrays on NVIDIA GPUs"):
+ *
+ *   2-D, Section 2, the identity (A (x) B) vec(X) = vec(B X A^T):
+ *       Y_p = B * X_p * A^T                       for p = 0 .. batch-1
+ *   3-D, Section 2.1, the triple summation and its vec form:
+ *       vec(Y_p) = (A (x) B (x) C) vec(X_p)
+ *     which is the paper's K(C, B, A): C acts on the fastest memory index,
+ *     B on the middle one and A on the slowest.  With operand element
+ *     (a, b, c) stored at a*n*n + b*n + c:
+ *       Y_p(i, j, k) = sum_{a,b,c} A(i, a) B(j, b) C(k, c) X_p(a, b, c).
+ *   Both are the batched update of Section 2.2 with alpha = 1, beta = 0 and
+ *   op = N everywhere (the setting the paper measures in Section 5).
+ *
+ * Layout (Section 3): every matrix is n x n column-major with leading
+ * dimension n (element (i, j) at i + n*j); operands are packed back to back
+ * with the smallest strides (n*n for 2-D, n*n*n for 3-D), 2-D operands
+ * column-major.  One rule covers both: vec(Y_p) = kron(F1, kron(F2, ...))
+ * vec(X_p) on memory-order vectors, with the factors in argument order.
+ * 1 <= n <= 16 (the paper's size range, Table 1).
+ *
+ * Ownership: the caller owns all memory; every pointer is a device pointer
+ * (the grouped and backward entry points also take a caller-owned device
+ * workspace; see their notes).  The library never allocates device memory
+ * (the work-array convention of Section 4).  Calls are asynchronous on
+ * `stream` (0 = the null stream) unless noted.
+ *
+ * Aliasing: X and Y must not overlap; X == Y is rejected, partial overlap is
+ * undefined.  Y is write-only (beta = 0): its previous contents, NaN
+ * included, never reach the result.
+ *
+ * Return value: 0 on success; -k when argument k (1-based) is invalid;
+ * a positive hipError_t when a HIP call fails.  batch == 0 returns 0 and
+ * launches nothing.  kron_status_string() names any status.
+ */
+#ifndef KRON_H
+#define KRON_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define KRON_SUCCESS 0
+#define KRON_MAX_N 16
+
+/* Precision modes (the grouped descriptors and the autotuner use them). */
+enum kron_mode {
+  KRON_MODE_F32 = 0,    /* FP32 in/out, FP32 products and sums */
+  KRON_MODE_F64 = 1,    /* FP64 in/out, FP64 products and sums */
+  KRON_MODE_BF16X3 = 2, /* FP32 in/out; each FP32 factor split into bf16 hi + lo,
+                           products hi*hi' + hi*lo' + lo*hi' on bf16 matrix cores,
+                           FP32 sums */
+  KRON_MODE_BF16 = 3    /* bf16 storage of A, B, C, X, Y (uint16_t bit patterns),
+                           FP32 sums, intermediates kept as bf16 hi + lo pairs,
+                           output rounded to nearest even */
+};
+
+/* ---- plain forward ------------------------------------------------------- */
+
+/* Y_p = B X_p A^T (2-D, Section 2), FP32.  A, B: n*n; X, Y: batch*n*n. */
+int kron2d_batched_f32(int n, const float* A, const float* B, const float* X,
+                       float* Y, int64_t batch, hipStream_t stream);
+/* Same in FP64. */
+int kron2d_batched_f64(int n, const double* A, const double* B, const double* X,
+                       double* Y, int64_t batch, hipStream_t stream);
+
+/* vec(Y_p) = (A (x) B (x) C) vec(X_p) (3-D, Section 2.1), FP32.
+   A, B, C: n*n; X, Y: batch*n^3. */
+int kron3d_batched_f32(int n, const float* A, const float* B, const float* C,
+                       const float* X, float* Y, int64_t batch, hipStream_t stream);
+/* Same in FP64. */
+int kron3d_batched_f64(int n, const double* A, const double* B, const double* C,
+                       const double* X, double* Y, int64_t batch, hipStream_t stream);
+
+/* ---- precision modes (same operations, same layouts) -------------------- */
+
+/* FP32 in/out computed with the bf16x3 split on bf16 matrix cores
+   (KRON_MODE_BF16X3).  Normwise error stays within FP32's 1e-5 gate. */
+int kron2d_batched_f32_bf16x3(int n, const float* A, const float* B, const float* X,
+                              float* Y, int64_t batch, hipStream_t stream);
+int kron3d_batched_f32_bf16x3(int n, const float* A, const float* B, const float* C,
+                              const float* X, float* Y, int64_t batch, hipStream_t stream);
+
+/* bf16 storage (KRON_MODE_BF16): every array holds bf16 bit patterns
+   (uint16_t); sums in FP32; Y rounded to nearest even. */
+int kron2d_batched_bf16(int n, const uint16_t* A, const uint16_t* B, const uint16_t* X,
+                        uint16_t* Y, int64_t batch, hipStream_t stream);
+int kron3d_batched_bf16(int n, const uint16_t* A, const uint16_t* B, const uint16_t* C,
+                        const uint16_t* X, uint16_t* Y, int64_t batch, hipStream_t stream);
+
+/* ---- transposed action (the adjoint) ------------------------------------ */
+
+/* The same actions with every factor transposed: Y_p = B^T X_p A (2-D) and
+   vec(Y_p) = (A^T (x) B^T (x) C^T) vec(X_p) (3-D).  The paper transposes the
+   constant matrices once instead of per operand (Section 2.2); here the
+   transpose is folded into how each wave loads the factors.  This is the
+   gradient with respect to X. */
+int kron2d_batched_adjoint_f32(int n, const float* A, const float* B, const float* X,
+                               float* Y, int64_t batch, hipStream_t stream);
+int kron3d_batched_adjoint_f32(int n, const float* A, const float* B, const float* C,
+                               const float* X, float* Y, int64_t batch, hipStream_t stream);
+int kron2d_batched_adjoint_f64(int n, const double* A, const double* B, const double* X,
+                               double* Y, int64_t batch, hipStream_t stream);
+int kron3d_batched_adjoint_f64(int n, const double* A, const double* B, const double* C,
+                               const double* X, double* Y, int64_t batch, hipStream_t stream);
+
+/* ---- status -------------------------------------------------------------- */
+
+/* Static string describing a status returned by any entry point. */
+const char* kron_status_string(int status);
+
+/* Library version and build target, e.g. "kron 0.1 gfx950". */
+const char* kron_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KRON_H */

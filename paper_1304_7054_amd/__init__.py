@@ -1,0 +1,30 @@
+"""MI355X (gfx950) batched Kronecker-product action.
+
+The compute lives in ``libkron.so`` (hand-written HIP kernels, C ABI declared
+in ``include/kron.h``).  This package is its thin Python binding: the
+functions carry the names of the C entry points and only marshal arguments.
+"""
+from ._binding import (  # noqa: F401
+    KronError,
+    LIB_PATH,
+    MODE_BF16,
+    MODE_BF16X3,
+    MODE_F32,
+    MODE_F64,
+    SIGNATURES,
+    kron2d_batched_adjoint_f32,
+    kron2d_batched_adjoint_f64,
+    kron2d_batched_bf16,
+    kron2d_batched_f32,
+    kron2d_batched_f32_bf16x3,
+    kron2d_batched_f64,
+    kron3d_batched_adjoint_f32,
+    kron3d_batched_adjoint_f64,
+    kron3d_batched_bf16,
+    kron3d_batched_f32,
+    kron3d_batched_f32_bf16x3,
+    kron3d_batched_f64,
+    lib,
+    status_string,
+    version,
+)

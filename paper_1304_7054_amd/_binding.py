@@ -1,0 +1,174 @@
+"""ctypes binding of libkron (include/kron.h): argument marshalling only.
+
+Every function here has the name of the C entry point it calls.  Arrays are
+torch tensors on the GPU (their storage is passed as a raw pointer); the
+binding checks device, dtype, contiguity and sizes so that a kernel never
+reads or writes outside the tensors it is given, then calls the library on
+the current (or given) stream.  All arithmetic happens in the HIP kernels;
+there is no other code path.  If libkron.so is missing, every call raises.
+"""
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libkron.so")
+
+MODE_F32, MODE_F64, MODE_BF16X3, MODE_BF16 = 0, 1, 2, 3
+
+
+class KronError(RuntimeError):
+    """A non-zero status returned by libkron."""
+
+    def __init__(self, func, status, text):
+        super().__init__(f"{func} returned {status}: {text}")
+        self.status = status
+
+
+_LIB = None
+
+# (name, argument kinds); 'i' int, 'l' int64, 'p' pointer, 's' stream, 'z' size_t
+SIGNATURES = {
+    "kron2d_batched_f32": "ipppplS",
+    "kron2d_batched_f64": "ipppplS",
+    "kron3d_batched_f32": "ippppplS",
+    "kron3d_batched_f64": "ippppplS",
+    "kron2d_batched_f32_bf16x3": "ipppplS",
+    "kron3d_batched_f32_bf16x3": "ippppplS",
+    "kron2d_batched_bf16": "ipppplS",
+    "kron3d_batched_bf16": "ippppplS",
+    "kron2d_batched_adjoint_f32": "ipppplS",
+    "kron3d_batched_adjoint_f32": "ippppplS",
+    "kron2d_batched_adjoint_f64": "ipppplS",
+    "kron3d_batched_adjoint_f64": "ippppplS",
+}
+
+_CT = {"i": ctypes.c_int, "l": ctypes.c_int64, "p": ctypes.c_void_p, "S": ctypes.c_void_p,
+       "z": ctypes.c_size_t}
+
+
+def lib():
+    """The loaded libkron (raises if it has not been built)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libkron.so not found at {LIB_PATH}; build it with "
+                               "`python paper_1304_7054_amd/build.py` (hipcc, gfx950)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, kinds in SIGNATURES.items():
+            f = getattr(L, name)
+            f.argtypes = [_CT[k] for k in kinds]
+            f.restype = ctypes.c_int
+        L.kron_status_string.argtypes = [ctypes.c_int]
+        L.kron_status_string.restype = ctypes.c_char_p
+        L.kron_version.argtypes = []
+        L.kron_version.restype = ctypes.c_char_p
+        _LIB = L
+    return _LIB
+
+
+def status_string(status: int) -> str:
+    return lib().kron_status_string(int(status)).decode()
+
+
+def version() -> str:
+    return lib().kron_version().decode()
+
+
+def _stream(stream):
+    if stream is None:
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _arr(t, dtype, min_numel, what):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{what} must be a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{what} must live on the GPU, not {t.device}")
+    if t.dtype != dtype:
+        raise TypeError(f"{what} must have dtype {dtype}, not {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    if t.numel() < min_numel:
+        raise ValueError(f"{what} holds {t.numel()} elements, needs {min_numel}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _call(name, *args):
+    rc = getattr(lib(), name)(*args)
+    if rc != 0:
+        raise KronError(name, rc, status_string(rc))
+    return rc
+
+
+def _dim_call(name, dim, dtype, n, mats, X, Y, batch, stream):
+    n, batch = int(n), int(batch)
+    if not 1 <= n <= 16:
+        raise ValueError(f"n must be in 1..16, got {n}")
+    if batch < 0:
+        raise ValueError("batch must be >= 0")
+    ptrs = [_arr(M, dtype, n * n, f"factor {i}") for i, M in enumerate(mats)]
+    size = batch * n ** dim
+    px = _arr(X, dtype, size, "X")
+    py = _arr(Y, dtype, size, "Y")
+    if X.data_ptr() == Y.data_ptr() and size > 0:
+        raise ValueError("X and Y must not overlap")
+    return _call(name, n, *ptrs, px, py, batch, _stream(stream))
+
+
+def kron2d_batched_f32(n, A, B, X, Y, batch, stream=None):
+    """Y_p = B X_p A^T, FP32 (see include/kron.h)."""
+    return _dim_call("kron2d_batched_f32", 2, torch.float32, n, (A, B), X, Y, batch, stream)
+
+
+def kron2d_batched_f64(n, A, B, X, Y, batch, stream=None):
+    return _dim_call("kron2d_batched_f64", 2, torch.float64, n, (A, B), X, Y, batch, stream)
+
+
+def kron3d_batched_f32(n, A, B, C, X, Y, batch, stream=None):
+    """vec(Y_p) = (A kron B kron C) vec(X_p), FP32 (see include/kron.h)."""
+    return _dim_call("kron3d_batched_f32", 3, torch.float32, n, (A, B, C), X, Y, batch, stream)
+
+
+def kron3d_batched_f64(n, A, B, C, X, Y, batch, stream=None):
+    return _dim_call("kron3d_batched_f64", 3, torch.float64, n, (A, B, C), X, Y, batch, stream)
+
+
+def kron2d_batched_f32_bf16x3(n, A, B, X, Y, batch, stream=None):
+    return _dim_call("kron2d_batched_f32_bf16x3", 2, torch.float32, n, (A, B), X, Y, batch, stream)
+
+
+def kron3d_batched_f32_bf16x3(n, A, B, C, X, Y, batch, stream=None):
+    return _dim_call("kron3d_batched_f32_bf16x3", 3, torch.float32, n, (A, B, C), X, Y, batch, stream)
+
+
+def kron2d_batched_bf16(n, A, B, X, Y, batch, stream=None):
+    """bf16 storage: tensors of dtype torch.bfloat16 (or int16/uint16 bit patterns viewed as bfloat16)."""
+    return _dim_call("kron2d_batched_bf16", 2, torch.bfloat16, n, (A, B), X, Y, batch, stream)
+
+
+def kron3d_batched_bf16(n, A, B, C, X, Y, batch, stream=None):
+    return _dim_call("kron3d_batched_bf16", 3, torch.bfloat16, n, (A, B, C), X, Y, batch, stream)
+
+
+def kron2d_batched_adjoint_f32(n, A, B, X, Y, batch, stream=None):
+    """Y_p = B^T X_p A, FP32."""
+    return _dim_call("kron2d_batched_adjoint_f32", 2, torch.float32, n, (A, B), X, Y, batch, stream)
+
+
+def kron3d_batched_adjoint_f32(n, A, B, C, X, Y, batch, stream=None):
+    return _dim_call("kron3d_batched_adjoint_f32", 3, torch.float32, n, (A, B, C), X, Y, batch, stream)
+
+
+def kron2d_batched_adjoint_f64(n, A, B, X, Y, batch, stream=None):
+    return _dim_call("kron2d_batched_adjoint_f64", 2, torch.float64, n, (A, B), X, Y, batch, stream)
+
+
+def kron3d_batched_adjoint_f64(n, A, B, C, X, Y, batch, stream=None):
+    return _dim_call("kron3d_batched_adjoint_f64", 3, torch.float64, n, (A, B, C), X, Y, batch, stream)

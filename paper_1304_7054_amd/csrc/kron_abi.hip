@@ -1,0 +1,181 @@
+// C ABI of libkron: argument checks, status codes and dispatch to the
+// per-mode launchers.  The declarations and their documentation are in
+// include/kron.h.
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cstdint>
+#include <cstring>
+
+#include "kron.h"
+#include "kron_runtime.hpp"
+
+namespace kron {
+
+int device_cus() {
+  static std::atomic<int> cache[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+  int v = cache[dev].load(std::memory_order_relaxed);
+  if (v == 0) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 1;
+    cache[dev].store(cus, std::memory_order_relaxed);
+    v = cus;
+  }
+  return v;
+}
+
+namespace {
+std::atomic<int> g_blocks_per_cu[4][2][17];
+}
+
+int tuned_blocks_per_cu(int mode, int dim, int n) {
+  if (mode < 0 || mode > 3 || dim < 2 || dim > 3 || n < 1 || n > 16) return 0;
+  return g_blocks_per_cu[mode][dim - 2][n].load(std::memory_order_relaxed);
+}
+
+void set_tuned_blocks_per_cu(int mode, int dim, int n, int blocks) {
+  if (mode < 0 || mode > 3 || dim < 2 || dim > 3 || n < 1 || n > 16) return;
+  g_blocks_per_cu[mode][dim - 2][n].store(blocks < 0 ? 0 : blocks, std::memory_order_relaxed);
+}
+
+}  // namespace kron
+
+namespace {
+
+// Launch errors surface through hipGetLastError; return them as positive codes.
+int finish_launch(int rc) {
+  if (rc != 0) return rc;
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? 0 : (int)e;
+}
+
+// Common checks of the forward entry points.  Argument positions follow the
+// C signatures: n is 1, then the factors, then X, Y, batch.
+int check2d(int n, const void* A, const void* B, const void* X, const void* Y, int64_t batch) {
+  if (n < 1 || n > KRON_MAX_N) return -1;
+  if (!A) return -2;
+  if (!B) return -3;
+  if (!X) return -4;
+  if (!Y || Y == X) return -5;
+  if (batch < 0) return -6;
+  return 0;
+}
+
+int check3d(int n, const void* A, const void* B, const void* C, const void* X, const void* Y, int64_t batch) {
+  if (n < 1 || n > KRON_MAX_N) return -1;
+  if (!A) return -2;
+  if (!B) return -3;
+  if (!C) return -4;
+  if (!X) return -5;
+  if (!Y || Y == X) return -6;
+  if (batch < 0) return -7;
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int kron2d_batched_f32(int n, const float* A, const float* B, const float* X, float* Y, int64_t batch,
+                       hipStream_t stream) {
+  if (int rc = check2d(n, A, B, X, Y, batch)) return rc;
+  if (batch == 0) return 0;
+  return finish_launch(kron::fwd2d_f32(n, A, B, X, Y, batch, stream, false));
+}
+
+int kron2d_batched_f64(int n, const double* A, const double* B, const double* X, double* Y, int64_t batch,
+                       hipStream_t stream) {
+  if (int rc = check2d(n, A, B, X, Y, batch)) return rc;
+  if (batch == 0) return 0;
+  return finish_launch(kron::fwd2d_f64(n, A, B, X, Y, batch, stream, false));
+}
+
+int kron3d_batched_f32(int n, const float* A, const float* B, const float* C, const float* X, float* Y,
+                       int64_t batch, hipStream_t stream) {
+  if (int rc = check3d(n, A, B, C, X, Y, batch)) return rc;
+  if (batch == 0) return 0;
+  return finish_launch(kron::fwd3d_f32(n, A, B, C, X, Y, batch, stream, false));
+}
+
+int kron3d_batched_f64(int n, const double* A, const double* B, const double* C, const double* X, double* Y,
+                       int64_t batch, hipStream_t stream) {
+  if (int rc = check3d(n, A, B, C, X, Y, batch)) return rc;
+  if (batch == 0) return 0;
+  return finish_launch(kron::fwd3d_f64(n, A, B, C, X, Y, batch, stream, false));
+}
+
+int kron2d_batched_f32_bf16x3(int n, const float* A, const float* B, const float* X, float* Y, int64_t batch,
+                              hipStream_t stream) {
+  if (int rc = check2d(n, A, B, X, Y, batch)) return rc;
+  if (batch == 0) return 0;
+  return finish_launch(kron::fwd2d_bf16x3(n, A, B, X, Y, batch, stream));
+}
+
+int kron3d_batched_f32_bf16x3(int n, const float* A, const float* B, const float* C, const float* X, float* Y,
+                              int64_t batch, hipStream_t stream) {
+  if (int rc = check3d(n, A, B, C, X, Y, batch)) return rc;
+  if (batch == 0) return 0;
+  return finish_launch(kron::fwd3d_bf16x3(n, A, B, C, X, Y, batch, stream));
+}
+
+int kron2d_batched_bf16(int n, const uint16_t* A, const uint16_t* B, const uint16_t* X, uint16_t* Y,
+                        int64_t batch, hipStream_t stream) {
+  if (int rc = check2d(n, A, B, X, Y, batch)) return rc;
+  if (batch == 0) return 0;
+  return finish_launch(kron::fwd2d_bf16(n, A, B, X, Y, batch, stream));
+}
+
+int kron3d_batched_bf16(int n, const uint16_t* A, const uint16_t* B, const uint16_t* C, const uint16_t* X,
+                        uint16_t* Y, int64_t batch, hipStream_t stream) {
+  if (int rc = check3d(n, A, B, C, X, Y, batch)) return rc;
+  if (batch == 0) return 0;
+  return finish_launch(kron::fwd3d_bf16(n, A, B, C, X, Y, batch, stream));
+}
+
+int kron2d_batched_adjoint_f32(int n, const float* A, const float* B, const float* X, float* Y, int64_t batch,
+                               hipStream_t stream) {
+  if (int rc = check2d(n, A, B, X, Y, batch)) return rc;
+  if (batch == 0) return 0;
+  return finish_launch(kron::fwd2d_f32(n, A, B, X, Y, batch, stream, true));
+}
+
+int kron3d_batched_adjoint_f32(int n, const float* A, const float* B, const float* C, const float* X, float* Y,
+                               int64_t batch, hipStream_t stream) {
+  if (int rc = check3d(n, A, B, C, X, Y, batch)) return rc;
+  if (batch == 0) return 0;
+  return finish_launch(kron::fwd3d_f32(n, A, B, C, X, Y, batch, stream, true));
+}
+
+int kron2d_batched_adjoint_f64(int n, const double* A, const double* B, const double* X, double* Y,
+                               int64_t batch, hipStream_t stream) {
+  if (int rc = check2d(n, A, B, X, Y, batch)) return rc;
+  if (batch == 0) return 0;
+  return finish_launch(kron::fwd2d_f64(n, A, B, X, Y, batch, stream, true));
+}
+
+int kron3d_batched_adjoint_f64(int n, const double* A, const double* B, const double* C, const double* X,
+                               double* Y, int64_t batch, hipStream_t stream) {
+  if (int rc = check3d(n, A, B, C, X, Y, batch)) return rc;
+  if (batch == 0) return 0;
+  return finish_launch(kron::fwd3d_f64(n, A, B, C, X, Y, batch, stream, true));
+}
+
+const char* kron_status_string(int status) {
+  if (status == 0) return "success";
+  if (status < 0) {
+    static const char* names[] = {"invalid argument 1", "invalid argument 2",  "invalid argument 3",
+                                  "invalid argument 4", "invalid argument 5",  "invalid argument 6",
+                                  "invalid argument 7", "invalid argument 8",  "invalid argument 9",
+                                  "invalid argument 10", "invalid argument 11", "invalid argument 12",
+                                  "invalid argument 13", "invalid argument 14", "invalid argument 15"};
+    int k = -status;
+    return k <= 15 ? names[k - 1] : "invalid argument";
+  }
+  return hipGetErrorString((hipError_t)status);
+}
+
+const char* kron_version(void) { return "kron 0.1 gfx950"; }
+
+}  // extern "C"

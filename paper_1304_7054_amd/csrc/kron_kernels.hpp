@@ -1,0 +1,365 @@
+// Per-tile routines of the batched Kronecker action (2-D and 3-D).
+//
+// 2-D (Section 2, (A (x) B) vec(X) = vec(B X A^T)).  In memory an operand is
+// X(u, v) at u*n + v (u = column of the column-major matrix, the slow index;
+// v = row, the fast index), and Y(i, j) = sum_{u,v} A(i, u) B(j, v) X(u, v).
+//   load    lane (L, g) holds X(u = slot L, v = slots 4g..4g+3)
+//   stage 1 contract v with B, data as MFMA operand A  -> rows u, column j
+//   stage 2 contract u with A, data as MFMA operand A  -> rows j, column i
+//   store   lane (L, g) holds Y(i = slot L, j = slots drow(g, 0..3))
+//
+// 3-D (Section 2.1; the library's (A (x) B (x) C) is the paper's K(C, B, A)).
+// Element (a, b, c) at a*n^2 + b*n + c and
+// Y(i, j, k) = sum A(i, a) B(j, b) C(k, c) X(a, b, c).
+//   load    lane (L, g), slab b holds X(a = slot L, b, c = slots 4g..4g+3)
+//   stage 1 contract c with C, data as operand A  -> rows a, column k   (per slab b)
+//   stage 2 contract a with A, data as operand B  -> rows i, column k   (per slab b)
+//   exchange lane groups <-> slabs                 -> slab i, slots b on (g, s)
+//   stage 3 contract b with B, data as operand A  -> rows k, column j   (per slab i)
+//   store   lane (L, g), slab i holds Y(i, j = slot L, k = slots drow(g, 0..3))
+// Unlike the paper's Algorithm 1 there is no intermediate array in memory:
+// all three mode products run on data held in registers.
+#pragma once
+
+#include "kron_tile.hpp"
+
+namespace kron {
+
+// ---- memory access of four elements ------------------------------------------------
+
+template <typename io_t>
+struct Mem;
+
+template <>
+struct Mem<float> {
+  using acc = f32x4;
+  static constexpr int kAlign = 16;
+  __device__ static f32x4 load4(const float* p) { return __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(p)); }
+  __device__ static void store4(float* p, const f32x4& v) { __builtin_nontemporal_store(v, reinterpret_cast<f32x4*>(p)); }
+  __device__ static float load1(const float* p) { return __builtin_nontemporal_load(p); }
+  __device__ static void store1(float* p, float v) { __builtin_nontemporal_store(v, p); }
+};
+
+template <>
+struct Mem<double> {
+  using acc = f64x4;
+  typedef double f64x2 __attribute__((ext_vector_type(2)));
+  static constexpr int kAlign = 16;
+  __device__ static f64x4 load4(const double* p) {
+    f64x2 a = __builtin_nontemporal_load(reinterpret_cast<const f64x2*>(p));
+    f64x2 b = __builtin_nontemporal_load(reinterpret_cast<const f64x2*>(p + 2));
+    return f64x4{a[0], a[1], b[0], b[1]};
+  }
+  __device__ static void store4(double* p, const f64x4& v) {
+    __builtin_nontemporal_store(f64x2{v[0], v[1]}, reinterpret_cast<f64x2*>(p));
+    __builtin_nontemporal_store(f64x2{v[2], v[3]}, reinterpret_cast<f64x2*>(p + 2));
+  }
+  __device__ static double load1(const double* p) { return __builtin_nontemporal_load(p); }
+  __device__ static void store1(double* p, double v) { __builtin_nontemporal_store(v, p); }
+};
+
+// bf16 storage: values are widened to FP32 on load and rounded to nearest even on store
+template <>
+struct Mem<uint16_t> {
+  using acc = f32x4;
+  static constexpr int kAlign = 8;
+  __device__ static f32x4 load4(const uint16_t* p) {
+    u16x4 b = __builtin_nontemporal_load(reinterpret_cast<const u16x4*>(p));
+    return f32x4{from_bf16(bits_to_bf16(b[0])), from_bf16(bits_to_bf16(b[1])), from_bf16(bits_to_bf16(b[2])),
+                 from_bf16(bits_to_bf16(b[3]))};
+  }
+  __device__ static void store4(uint16_t* p, const f32x4& v) {
+    u16x4 b = {bf16_to_bits(to_bf16(v[0])), bf16_to_bits(to_bf16(v[1])), bf16_to_bits(to_bf16(v[2])),
+               bf16_to_bits(to_bf16(v[3]))};
+    __builtin_nontemporal_store(b, reinterpret_cast<u16x4*>(p));
+  }
+  __device__ static float load1(const uint16_t* p) { return from_bf16(bits_to_bf16(__builtin_nontemporal_load(p))); }
+  __device__ static void store1(uint16_t* p, float v) { __builtin_nontemporal_store(bf16_to_bits(to_bf16(v)), p); }
+};
+
+template <typename V>
+__device__ __forceinline__ bool all_finite(const V& v) {
+  return __builtin_isfinite(v[0]) && __builtin_isfinite(v[1]) && __builtin_isfinite(v[2]) && __builtin_isfinite(v[3]);
+}
+
+// Offset (elements, relative to the tile's first operand) and packed-operand
+// number contributed by one axis.  `stride` is the element stride of the axis
+// inside an operand (n^2, n or 1); `opmul` its packed-operand multiplier
+// (Q^2, Q or 1); E the operand size n^d.
+template <int N, int E>
+struct AxisPart {
+  int off, op;
+  bool valid;
+  __device__ __forceinline__ AxisPart(int slot, int stride, int opmul) {
+    Slot<N> s(slot);
+    op = s.sub * opmul;
+    off = op * E + s.idx * stride;
+    valid = s.valid;
+  }
+};
+
+// ---- 2-D tile ---------------------------------------------------------------------
+
+template <class M, int N, bool kVec, bool kTrans>
+struct Tile2D {
+  using io_t = typename M::io_t;
+  using acc_t = typename M::acc_t;
+  using fac_t = typename M::fac_t;
+  static constexpr int Q = Geo<N>::Q;
+  static constexpr int kOps = Q * Q;  // operands per tile
+  static constexpr int E = N * N;     // elements per operand
+  static constexpr bool kStoreVec = kVec && (M::drow(0, 1) == 1);
+
+  fac_t fB, fA;
+  AxisPart<N, E> pL;            // slot L on the slow axis (load and store)
+  int offI[4], opI[4];          // load: fast slots 4g + s
+  bool vI[4];
+  int offO[4], opO[4];          // store: fast slots drow(g, r)
+  bool vO[4];
+
+  __device__ __forceinline__ Tile2D(const io_t* A, const io_t* B, int L, int g) : pL(L, N, Q) {
+    fB = M::template load_fac<N, kTrans>(B, L, g, 0);
+    fA = M::template load_fac<N, kTrans>(A, L, g, 1);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      AxisPart<N, E> pi(4 * g + s, 1, 1), po(M::drow(g, s), 1, 1);
+      offI[s] = pi.off; opI[s] = pi.op; vI[s] = pi.valid;
+      offO[s] = po.off; opO[s] = po.op; vO[s] = po.valid;
+    }
+  }
+
+  // rem = operands from the tile's first one to the end of the batch (>= 1);
+  // only >= 0 restricts the access to that one operand of the tile.
+  __device__ static __forceinline__ bool take(int op, int64_t rem, int only) {
+    return op < rem && (only < 0 || op == only);
+  }
+
+  __device__ __forceinline__ acc_t load(const io_t* Xt, int64_t rem, int only = -1) const {
+    acc_t x;
+    if constexpr (N == 16 && kVec) {
+      x = Mem<io_t>::load4(Xt + pL.off + offI[0]);
+    } else if constexpr (kVec) {
+      bool ok = pL.valid && vI[0] && take(pL.op + opI[0], rem, only);
+      if (ok) x = Mem<io_t>::load4(Xt + pL.off + offI[0]);
+      else x = acc_t{0, 0, 0, 0};
+    } else {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        bool ok = pL.valid && vI[s] && take(pL.op + opI[s], rem, only);
+        x[s] = ok ? Mem<io_t>::load1(Xt + pL.off + offI[s]) : 0;
+      }
+    }
+    return x;
+  }
+
+  __device__ __forceinline__ acc_t compute(const acc_t& x) const { return M::da(fA, M::da_in(fB, x)); }
+
+  __device__ __forceinline__ void store(io_t* Yt, int64_t rem, const acc_t& y, int only = -1) const {
+    if constexpr (N == 16 && kStoreVec) {
+      Mem<io_t>::store4(Yt + pL.off + offO[0], y);
+    } else if constexpr (kStoreVec) {
+      if (pL.valid && vO[0] && take(pL.op + opO[0], rem, only)) Mem<io_t>::store4(Yt + pL.off + offO[0], y);
+    } else {
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (pL.valid && vO[r] && take(pL.op + opO[r], rem, only)) Mem<io_t>::store1(Yt + pL.off + offO[r], y[r]);
+    }
+  }
+
+  // Packed tiles (Q > 1): a NaN or Inf in one operand would reach its tile
+  // neighbours through the zero blocks of the factor tiles (0 * Inf = NaN).
+  // When a tile's result holds any non-finite value, it is redone one
+  // operand at a time so that IEEE propagation stays inside each operand.
+  __device__ __forceinline__ void finish(const io_t* Xt, io_t* Yt, int64_t rem, const acc_t& y) const {
+    if constexpr (kOps > 1) {
+      if (__any(!all_finite(y))) {
+        const int last = rem < kOps ? (int)rem : kOps;
+        for (int o = 0; o < last; ++o) store(Yt, rem, compute(load(Xt, rem, o)), o);
+        return;
+      }
+    }
+    store(Yt, rem, y);
+  }
+};
+
+// ---- 3-D tile ---------------------------------------------------------------------
+
+template <class M, int N, bool kVec, bool kTrans>
+struct Tile3D {
+  using io_t = typename M::io_t;
+  using acc_t = typename M::acc_t;
+  using fac_t = typename M::fac_t;
+  static constexpr int Q = Geo<N>::Q;
+  static constexpr int kOps = Q * Q * Q;
+  static constexpr int E = N * N * N;
+  static constexpr bool kStoreVec = kVec && (M::drow(0, 1) == 1);
+
+  fac_t fC, fA, fB;
+  AxisPart<N, E> pLi;   // load: slot L on the slow axis a
+  AxisPart<N, E> pLo;   // store: slot L on the middle axis j
+  int offI[4], opI[4];  // load: fast slots 4g + s
+  bool vI[4];
+  int offO[4], opO[4];  // store: fast slots drow(g, r)
+  bool vO[4];
+
+  __device__ __forceinline__ Tile3D(const io_t* A, const io_t* B, const io_t* C, int L, int g)
+      : pLi(L, N * N, Q * Q), pLo(L, N, Q) {
+    fC = M::template load_fac<N, kTrans>(C, L, g, 0);
+    fA = M::template load_fac<N, kTrans>(A, L, g, 1);
+    fB = M::template load_fac<N, kTrans>(B, L, g, 0);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      AxisPart<N, E> pi(4 * g + s, 1, 1), po(M::drow(g, s), 1, 1);
+      offI[s] = pi.off; opI[s] = pi.op; vI[s] = pi.valid;
+      offO[s] = po.off; opO[s] = po.op; vO[s] = po.valid;
+    }
+  }
+
+  __device__ static __forceinline__ bool take(int op, int64_t rem, int only) {
+    return op < rem && (only < 0 || op == only);
+  }
+
+  __device__ __forceinline__ void load(const io_t* Xt, int64_t rem, acc_t (&t)[16], int only = -1) const {
+#pragma unroll
+    for (int b = 0; b < 16; ++b) {
+      AxisPart<N, E> pS(b, N, Q);  // slab on the middle axis
+      if constexpr (N == 16 && kVec) {
+        t[b] = Mem<io_t>::load4(Xt + pLi.off + pS.off + offI[0]);
+      } else if constexpr (kVec) {
+        bool ok = pS.valid && pLi.valid && vI[0] && take(pLi.op + pS.op + opI[0], rem, only);
+        if (ok) t[b] = Mem<io_t>::load4(Xt + pLi.off + pS.off + offI[0]);
+        else t[b] = acc_t{0, 0, 0, 0};
+      } else {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          bool ok = pS.valid && pLi.valid && vI[s] && take(pLi.op + pS.op + opI[s], rem, only);
+          t[b][s] = ok ? Mem<io_t>::load1(Xt + pLi.off + pS.off + offI[s]) : 0;
+        }
+      }
+    }
+  }
+
+  // t: loaded slabs in, results (slab i) out
+  __device__ __forceinline__ void compute(acc_t (&t)[16]) const {
+#pragma unroll
+    for (int b = 0; b < 16; ++b) t[b] = M::da_in(fC, t[b]);
+#pragma unroll
+    for (int b = 0; b < 16; ++b) t[b] = M::db(fA, t[b]);
+    exchange_groups_slabs(t);
+    acc_t y[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      // row i was held by lane group gi, register ri before the exchange
+      int gi = 0, ri = 0;
+#pragma unroll
+      for (int gg = 0; gg < 4; ++gg)
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr)
+          if (M::drow(gg, rr) == i) { gi = gg; ri = rr; }
+      acc_t z;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) z[s] = t[4 * gi + s][ri];
+      y[i] = M::da(fB, z);
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) t[i] = y[i];
+  }
+
+  __device__ __forceinline__ void store(io_t* Yt, int64_t rem, const acc_t (&t)[16], int only = -1) const {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      AxisPart<N, E> pS(i, N * N, Q * Q);  // slab on the slow axis
+      if constexpr (N == 16 && kStoreVec) {
+        Mem<io_t>::store4(Yt + pS.off + pLo.off + offO[0], t[i]);
+      } else if constexpr (kStoreVec) {
+        if (pS.valid && pLo.valid && vO[0] && take(pS.op + pLo.op + opO[0], rem, only))
+          Mem<io_t>::store4(Yt + pS.off + pLo.off + offO[0], t[i]);
+      } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (pS.valid && pLo.valid && vO[r] && take(pS.op + pLo.op + opO[r], rem, only))
+            Mem<io_t>::store1(Yt + pS.off + pLo.off + offO[r], t[i][r]);
+      }
+    }
+  }
+
+  // Same isolation rule as the 2-D tile: a packed tile whose result holds a
+  // non-finite value is recomputed one operand at a time.
+  __device__ __forceinline__ void finish(const io_t* Xt, io_t* Yt, int64_t rem, acc_t (&t)[16]) const {
+    if constexpr (kOps > 1) {
+      bool fin = true;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) fin = fin && all_finite(t[i]);
+      if (__any(!fin)) {
+        const int last = rem < kOps ? (int)rem : kOps;
+        for (int o = 0; o < last; ++o) {
+          load(Xt, rem, t, o);
+          compute(t);
+          store(Yt, rem, t, o);
+        }
+        return;
+      }
+    }
+    store(Yt, rem, t);
+  }
+};
+
+// ---- persistent kernels ---------------------------------------------------------------
+//
+// 256-thread workgroups; every wavefront walks the tiles with a grid stride.
+// The 2-D kernel keeps kTiles tiles in flight per wavefront.
+
+constexpr int kBlock = 256;
+
+template <class M, int N, bool kVec, bool kTrans, int kTiles>
+__global__ __launch_bounds__(kBlock) void kron2d_kernel(const typename M::io_t* __restrict__ A,
+                                                        const typename M::io_t* __restrict__ B,
+                                                        const typename M::io_t* __restrict__ X,
+                                                        typename M::io_t* __restrict__ Y, int64_t batch,
+                                                        int64_t ntiles) {
+  using T = Tile2D<M, N, kVec, kTrans>;
+  using acc_t = typename M::acc_t;
+  const int l = threadIdx.x & 63, L = l & 15, g = l >> 4;
+  const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * kBlock) >> 6;
+  const T tile(A, B, L, g);
+  for (int64_t base = wave * kTiles; base < ntiles; base += nwaves * kTiles) {
+    acc_t x[kTiles];
+#pragma unroll
+    for (int j = 0; j < kTiles; ++j) {
+      const int64_t t = base + j;
+      if (t < ntiles) x[j] = tile.load(X + t * T::kOps * T::E, batch - t * T::kOps);
+      else x[j] = acc_t{0, 0, 0, 0};
+    }
+#pragma unroll
+    for (int j = 0; j < kTiles; ++j) x[j] = tile.compute(x[j]);
+#pragma unroll
+    for (int j = 0; j < kTiles; ++j) {
+      const int64_t t = base + j;
+      if (t < ntiles) tile.finish(X + t * T::kOps * T::E, Y + t * T::kOps * T::E, batch - t * T::kOps, x[j]);
+    }
+  }
+}
+
+template <class M, int N, bool kVec, bool kTrans>
+__global__ __launch_bounds__(kBlock) void kron3d_kernel(const typename M::io_t* __restrict__ A,
+                                                        const typename M::io_t* __restrict__ B,
+                                                        const typename M::io_t* __restrict__ C,
+                                                        const typename M::io_t* __restrict__ X,
+                                                        typename M::io_t* __restrict__ Y, int64_t batch,
+                                                        int64_t ntiles) {
+  using T = Tile3D<M, N, kVec, kTrans>;
+  using acc_t = typename M::acc_t;
+  const int l = threadIdx.x & 63, L = l & 15, g = l >> 4;
+  const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * kBlock) >> 6;
+  const T tile(A, B, C, L, g);
+  for (int64_t t = wave; t < ntiles; t += nwaves) {
+    acc_t v[16];
+    tile.load(X + t * T::kOps * T::E, batch - t * T::kOps, v);
+    tile.compute(v);
+    tile.finish(X + t * T::kOps * T::E, Y + t * T::kOps * T::E, batch - t * T::kOps, v);
+  }
+}
+
+}  // namespace kron

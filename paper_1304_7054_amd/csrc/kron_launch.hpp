@@ -1,0 +1,120 @@
+// Host-side launch of the forward kernels: n dispatch, alignment choice and
+// grid size.  Included by one translation unit per precision mode.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cstdint>
+
+#include "kron_kernels.hpp"
+#include "kron_runtime.hpp"
+
+namespace kron {
+
+// Resident workgroups per CU for a kernel, queried once per instantiation.
+template <typename K>
+int occupancy_blocks(K kernel) {
+  static std::atomic<int> cached{0};
+  int v = cached.load(std::memory_order_relaxed);
+  if (v == 0) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(kernel), kBlock, 0) !=
+            hipSuccess ||
+        nb < 1)
+      nb = 1;
+    cached.store(nb, std::memory_order_relaxed);
+    v = nb;
+  }
+  return v;
+}
+
+// Workgroups to launch: enough to cover the work, at most `per_cu` (or the
+// occupancy limit when per_cu <= 0) on every CU.
+inline unsigned grid_blocks(int64_t waves_needed, int occ, int per_cu) {
+  const int64_t need = (waves_needed + kBlock / kWave - 1) / (kBlock / kWave);
+  const int64_t cap = (int64_t)device_cus() * (per_cu > 0 ? per_cu : occ);
+  int64_t g = need < cap ? need : cap;
+  if (g < 1) g = 1;
+  return (unsigned)g;
+}
+
+inline bool aligned_to(const void* p, int bytes) { return (reinterpret_cast<uintptr_t>(p) % bytes) == 0; }
+
+constexpr int k2dTiles = 4;
+
+template <class M, int N, bool kTrans>
+int launch2d_n(const typename M::io_t* A, const typename M::io_t* B, const typename M::io_t* X,
+               typename M::io_t* Y, int64_t batch, hipStream_t stream, int mode) {
+  using io_t = typename M::io_t;
+  constexpr int64_t ops = (int64_t)Geo<N>::Q * Geo<N>::Q;
+  const int64_t ntiles = (batch + ops - 1) / ops;
+  const int64_t waves = (ntiles + k2dTiles - 1) / k2dTiles;
+  const int per_cu = tuned_blocks_per_cu(mode, 2, N);
+  if constexpr (Geo<N>::kVec) {
+    if (aligned_to(X, Mem<io_t>::kAlign) && aligned_to(Y, Mem<io_t>::kAlign)) {
+      auto k = kron2d_kernel<M, N, true, kTrans, k2dTiles>;
+      hipLaunchKernelGGL(k, dim3(grid_blocks(waves, occupancy_blocks(k), per_cu)), dim3(kBlock), 0, stream, A, B,
+                         X, Y, batch, ntiles);
+      return 0;
+    }
+  }
+  auto k = kron2d_kernel<M, N, false, kTrans, k2dTiles>;
+  hipLaunchKernelGGL(k, dim3(grid_blocks(waves, occupancy_blocks(k), per_cu)), dim3(kBlock), 0, stream, A, B, X, Y,
+                     batch, ntiles);
+  return 0;
+}
+
+template <class M, int N, bool kTrans>
+int launch3d_n(const typename M::io_t* A, const typename M::io_t* B, const typename M::io_t* C,
+               const typename M::io_t* X, typename M::io_t* Y, int64_t batch, hipStream_t stream, int mode) {
+  using io_t = typename M::io_t;
+  constexpr int64_t ops = (int64_t)Geo<N>::Q * Geo<N>::Q * Geo<N>::Q;
+  const int64_t ntiles = (batch + ops - 1) / ops;
+  const int per_cu = tuned_blocks_per_cu(mode, 3, N);
+  if constexpr (Geo<N>::kVec) {
+    if (aligned_to(X, Mem<io_t>::kAlign) && aligned_to(Y, Mem<io_t>::kAlign)) {
+      auto k = kron3d_kernel<M, N, true, kTrans>;
+      hipLaunchKernelGGL(k, dim3(grid_blocks(ntiles, occupancy_blocks(k), per_cu)), dim3(kBlock), 0, stream, A, B,
+                         C, X, Y, batch, ntiles);
+      return 0;
+    }
+  }
+  auto k = kron3d_kernel<M, N, false, kTrans>;
+  hipLaunchKernelGGL(k, dim3(grid_blocks(ntiles, occupancy_blocks(k), per_cu)), dim3(kBlock), 0, stream, A, B, C,
+                     X, Y, batch, ntiles);
+  return 0;
+}
+
+#define KRON_N_CASES(F) \
+  F(1) F(2) F(3) F(4) F(5) F(6) F(7) F(8) F(9) F(10) F(11) F(12) F(13) F(14) F(15) F(16)
+
+template <class M, bool kTrans>
+int launch2d(int n, const typename M::io_t* A, const typename M::io_t* B, const typename M::io_t* X,
+             typename M::io_t* Y, int64_t batch, hipStream_t stream, int mode) {
+  switch (n) {
+#define KRON_CASE(NN) \
+  case NN:            \
+    return launch2d_n<M, NN, kTrans>(A, B, X, Y, batch, stream, mode);
+    KRON_N_CASES(KRON_CASE)
+#undef KRON_CASE
+    default:
+      return -1;
+  }
+}
+
+template <class M, bool kTrans>
+int launch3d(int n, const typename M::io_t* A, const typename M::io_t* B, const typename M::io_t* C,
+             const typename M::io_t* X, typename M::io_t* Y, int64_t batch, hipStream_t stream, int mode) {
+  switch (n) {
+#define KRON_CASE(NN) \
+  case NN:            \
+    return launch3d_n<M, NN, kTrans>(A, B, C, X, Y, batch, stream, mode);
+    KRON_N_CASES(KRON_CASE)
+#undef KRON_CASE
+    default:
+      return -1;
+  }
+}
+
+}  // namespace kron

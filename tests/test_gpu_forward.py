@@ -1,0 +1,201 @@
+"""GPU parity of the forward and transposed actions against the CPU oracle.
+
+Every call goes through the C ABI (ctypes binding).  Inputs are seeded
+(workloads module), results are compared with the FP64 oracle on the exact
+values the library received, element by element:
+  * FP32 plain / bf16x3: normwise and per-operand relative error <= 1e-5
+  * FP64: <= 1e-13
+  * bf16 storage: <= 1e-2 against the FP64 oracle on the bf16-rounded inputs
+Bit-exact cases (identity and permutation factors, small integers) compare
+every element exactly.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+from pins import cm, mat
+
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    import gpu_util as gu
+
+MODES = ["f32", "f64", "bf16x3", "bf16"]
+NS = list(range(1, 17))
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _oracle(dim, n, mats, X, batch, transpose=False):
+    if transpose:
+        mats = [cm(mat(M, n).T) for M in mats]
+    if dim == 2:
+        return oracle.kron2d(n, mats[0], mats[1], X, batch, "f64")
+    return oracle.kron3d(n, mats[0], mats[1], mats[2], X, batch, "f64")
+
+
+def _inputs(dim, n, batch, seed, mode):
+    rng = np.random.default_rng(seed)
+    mats = [rng.uniform(-1, 1, n * n) for _ in range(dim)]
+    X = rng.standard_normal(batch * n ** dim)
+    if mode in ("f32", "bf16x3", "adj_f32"):
+        mats = [m.astype(np.float32) for m in mats]
+        X = X.astype(np.float32)
+    return mats, X
+
+
+@pytest.mark.parametrize("n", NS)
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("mode", MODES + ["adj_f32", "adj_f64"])
+def test_forward_matches_oracle(mode, dim, n):
+    _need_gpu()
+    batch = gu.tiles_batch(dim, n)
+    mats, X = _inputs(dim, n, batch, 1000 * dim + n, mode)
+    got = gu.run(mode, dim, n, mats, X, batch)
+    exact_in = gu.rounded_inputs(mode, mats + [X])
+    want = _oracle(dim, n, exact_in[:-1], exact_in[-1], batch, transpose=mode.startswith("adj"))
+    norm, per = gu.errors(got, want, batch)
+    tol = gu.TOL[mode]
+    assert np.all(np.isfinite(got)), "unwritten or non-finite outputs"
+    assert norm <= tol, (mode, dim, n, norm)
+    if mode != "bf16":
+        assert per <= tol, (mode, dim, n, per)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 8, 12, 16])
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("mode", MODES)
+def test_identity_is_bit_exact(mode, dim, n):
+    _need_gpu()
+    batch = gu.tiles_batch(dim, n)
+    rng = np.random.default_rng(7)
+    X = rng.standard_normal(batch * n ** dim).astype(np.float32)
+    if mode == "bf16x3":
+        # the hi + lo split holds 16 significant bits; such values pass exactly
+        X = (X.view(np.uint32) & np.uint32(0xFFFFFF00)).view(np.float32)
+    I = workloads.identity_cm(n, np.float64)
+    got = gu.run(mode, dim, n, [I] * dim, X, batch)
+    want = gu.rounded_inputs(mode, [X])[0]
+    assert np.array_equal(got.astype(np.float64), want)
+
+
+def _perm_cm(n, perm):
+    P = np.zeros((n, n))
+    P[np.arange(n), perm] = 1.0
+    return cm(P)
+
+
+@pytest.mark.parametrize("n", [2, 3, 4, 6, 7, 10, 13, 16])
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("mode", MODES)
+def test_permutation_is_bit_exact(mode, dim, n):
+    """Distinct permutations per factor and index-coded X: Y must be the
+    gathered copy X[pa[i], pb[j](, pc[k])] exactly (factor <-> axis mapping)."""
+    _need_gpu()
+    batch = gu.tiles_batch(dim, n)
+    rng = np.random.default_rng(100 + n)
+    perms = [rng.permutation(n) for _ in range(dim)]
+    size = batch * n ** dim
+    # values exactly representable: 8 significant bits for bf16 storage, 16 for
+    # the bf16x3 split, 24 for FP32
+    limit = {"bf16": 256, "bf16x3": 1 << 16}.get(mode, 1 << 24)
+    X = (np.arange(size) % limit).astype(np.float64) + 1.0
+    got = gu.run(mode, dim, n, [_perm_cm(n, p) for p in perms], X, batch)
+    Xv = X.reshape((batch,) + (n,) * dim)
+    if dim == 2:
+        want = Xv[:, perms[0]][:, :, perms[1]]
+    else:
+        want = Xv[:, perms[0]][:, :, perms[1]][:, :, :, perms[2]]
+    assert np.array_equal(got.astype(np.float64), want.reshape(-1))
+
+
+@pytest.mark.parametrize("n", [3, 5, 8, 11, 16])
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("mode", MODES)
+def test_small_integers_are_bit_exact(mode, dim, n):
+    """A, B, C in {-2..2}, X in {-8..8}: all partial sums are exact in FP32,
+    so the library must equal the oracle bit for bit (bf16 storage: the
+    exact result rounded to bf16, nearest even)."""
+    _need_gpu()
+    batch = gu.tiles_batch(dim, n)
+    rng = np.random.default_rng(300 + n)
+    mats = [rng.integers(-2, 3, n * n).astype(np.float64) for _ in range(dim)]
+    X = rng.integers(-8, 9, batch * n ** dim).astype(np.float64)
+    got = gu.run(mode, dim, n, mats, X, batch)
+    want = _oracle(dim, n, mats, X, batch)
+    if mode == "bf16":
+        want = torch.from_numpy(want.astype(np.float32)).to(torch.bfloat16).float().numpy()
+    assert np.array_equal(got.astype(np.float64), want.astype(np.float64))
+
+
+@pytest.mark.parametrize("n", [2, 5, 16])
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("mode", ["f32", "f64", "bf16x3"])
+def test_nan_stays_in_its_operand(mode, dim, n):
+    """A NaN in one operand affects that operand's output only (packed tiles
+    included), and a NaN-filled Y never leaks into the result."""
+    _need_gpu()
+    batch = gu.tiles_batch(dim, n)
+    mats, X = _inputs(dim, n, batch, 55, mode)
+    q = batch // 2
+    X = X.copy()
+    X[q * n ** dim + (n ** dim) // 2] = np.nan
+    got = gu.run(mode, dim, n, mats, X, batch).reshape(batch, -1)
+    bad = [p for p in range(batch) if not np.all(np.isfinite(got[p]))]
+    assert bad == [q], bad
+    exact_in = gu.rounded_inputs(mode, mats + [X])
+    want = _oracle(dim, n, exact_in[:-1], exact_in[-1], batch).reshape(batch, -1)
+    keep = np.arange(batch) != q
+    norm, _ = gu.errors(got[keep], want[keep], batch - 1)
+    assert norm <= gu.TOL[mode]
+
+
+@pytest.mark.parametrize("n", [3, 16])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_unaligned_pointers(dim, n):
+    """Operand arrays starting one element past an aligned address take the
+    element-wise path and give the same result."""
+    _need_gpu()
+    batch = gu.tiles_batch(dim, n)
+    mats, X = _inputs(dim, n, batch, 77, "f32")
+    a = gu.run("f32", dim, n, mats, X, batch)
+    b = gu.run("f32", dim, n, mats, X, batch, x_offset=1, y_offset=3)
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_zero_batch_and_bad_arguments(dim):
+    _need_gpu()
+    import paper_1304_7054_amd as kron
+    n = 4
+    t = torch.zeros(n ** dim * 2, device=gu.DEV)
+    M = torch.zeros(n * n, device=gu.DEV)
+    fn = gu.FWD[("f32", dim)]
+    mats = [M] * dim
+    y = torch.full_like(t, 7.0)
+    assert fn(n, *mats, t, y, 0) == 0                           # batch 0: no-op
+    assert torch.all(y == 7.0)
+    raw = getattr(kron.lib(), fn.__name__)
+    p = [M.data_ptr()] * dim
+    assert raw(n, *p, t.data_ptr(), t.data_ptr(), 1, None) == -(dim + 3)   # X == Y
+    assert raw(0, *p, t.data_ptr(), y.data_ptr(), 1, None) == -1
+    assert raw(n, *p, t.data_ptr(), y.data_ptr(), -1, None) == -(dim + 4)
+    with pytest.raises(ValueError):
+        fn(n, *mats, t, t, 1)                                   # the binding rejects overlap too
+    with pytest.raises(ValueError):
+        fn(17, *mats, t, torch.empty_like(t), 1)
+    with pytest.raises(ValueError):
+        fn(n, *mats, t, torch.empty_like(t), 3)                 # too small for 3 operands
+
+
+def test_repeated_runs_are_bitwise_identical():
+    _need_gpu()
+    mats, X = _inputs(3, 16, 64, 5, "f32")
+    a = gu.run("f32", 3, 16, mats, X, 64)
+    b = gu.run("f32", 3, 16, mats, X, 64)
+    assert np.array_equal(a, b)
