@@ -112,6 +112,22 @@ int kron2d_batched_adjoint_f64(int n, const double* A, const double* B, const do
 int kron3d_batched_adjoint_f64(int n, const double* A, const double* B, const double* C,
                                const double* X, double* Y, int64_t batch, hipStream_t stream);
 
+/* ---- launch shape ----------------------------------------------------------- */
+
+/* How the kernels for (mode, dim, n) are launched: `blocks_per_cu` 256-thread
+   workgroups per compute unit (0 = as many as can be resident; -1 = back to
+   the built-in default) and a kernel `variant` (2-D: tiles in flight per
+   wavefront, 0 -> 4, 1 -> 8, 2 -> 2; 3-D: bit 0 = the next tile's loads are
+   issued before the current tile is computed, bit 1 = operands are read and
+   written in fully contiguous 1 KiB rows at the cost of a second
+   register exchange).  The paper
+   picks its kernel method by matrix size and fixes the number of thread
+   blocks (Sections 4 and 5); here the choice is a per-(mode, dim, n) table
+   that an autotuner can fill.  Process-wide, not thread-safe against
+   concurrent launches of the same (mode, dim, n).  Returns 0 or -k. */
+int kron_set_launch(int mode, int dim, int n, int blocks_per_cu, int variant);
+int kron_get_launch(int mode, int dim, int n, int* blocks_per_cu, int* variant);
+
 /* ---- status -------------------------------------------------------------- */
 
 /* Static string describing a status returned by any entry point. */

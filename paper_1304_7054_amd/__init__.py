@@ -24,6 +24,8 @@ from ._binding import (  # noqa: F401
     kron3d_batched_f32,
     kron3d_batched_f32_bf16x3,
     kron3d_batched_f64,
+    kron_get_launch,
+    kron_set_launch,
     lib,
     status_string,
     version,

@@ -64,6 +64,10 @@ def lib():
         L.kron_status_string.restype = ctypes.c_char_p
         L.kron_version.argtypes = []
         L.kron_version.restype = ctypes.c_char_p
+        L.kron_set_launch.argtypes = [ctypes.c_int] * 5
+        L.kron_set_launch.restype = ctypes.c_int
+        L.kron_get_launch.argtypes = [ctypes.c_int] * 3 + [ctypes.POINTER(ctypes.c_int)] * 2
+        L.kron_get_launch.restype = ctypes.c_int
         _LIB = L
     return _LIB
 
@@ -74,6 +78,18 @@ def status_string(status: int) -> str:
 
 def version() -> str:
     return lib().kron_version().decode()
+
+
+def kron_set_launch(mode, dim, n, blocks_per_cu, variant):
+    """Set the launch shape of (mode, dim, n); blocks_per_cu -1 restores the default."""
+    return _call("kron_set_launch", int(mode), int(dim), int(n), int(blocks_per_cu), int(variant))
+
+
+def kron_get_launch(mode, dim, n):
+    """(blocks_per_cu, variant) currently used for (mode, dim, n)."""
+    b, v = ctypes.c_int(0), ctypes.c_int(0)
+    _call("kron_get_launch", int(mode), int(dim), int(n), ctypes.byref(b), ctypes.byref(v))
+    return b.value, v.value
 
 
 def _stream(stream):

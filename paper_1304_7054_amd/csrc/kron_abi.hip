@@ -27,17 +27,47 @@ int device_cus() {
 }
 
 namespace {
-std::atomic<int> g_blocks_per_cu[4][2][17];
+// Launch shapes per (mode, dim - 2, n), packed as blocks_per_cu * 16 + variant.
+// -1 = not set: the built-in default applies.
+std::atomic<int> g_shape[4][2][17];
+
+void init_shapes() {
+  // thread-safe one-time initialisation (C++11 static local)
+  static const bool done = [] {
+    for (auto& m : g_shape)
+      for (auto& d : m)
+        for (auto& v : d) v.store(-1, std::memory_order_relaxed);
+    return true;
+  }();
+  (void)done;
 }
 
-int tuned_blocks_per_cu(int mode, int dim, int n) {
-  if (mode < 0 || mode > 3 || dim < 2 || dim > 3 || n < 1 || n > 16) return 0;
-  return g_blocks_per_cu[mode][dim - 2][n].load(std::memory_order_relaxed);
+// Built-in defaults, measured on MI355X (see the autotuner for the search).
+LaunchShape default_shape(int mode, int dim, int n) {
+  (void)mode;
+  (void)n;
+  if (dim == 3) return LaunchShape{0, 1};
+  return LaunchShape{0, 0};
+}
+}  // namespace
+
+LaunchShape launch_shape(int mode, int dim, int n) {
+  init_shapes();
+  if (mode < 0 || mode > 3 || dim < 2 || dim > 3 || n < 1 || n > 16) return LaunchShape{0, 0};
+  const int v = g_shape[mode][dim - 2][n].load(std::memory_order_relaxed);
+  if (v < 0) return default_shape(mode, dim, n);
+  return LaunchShape{v >> 4, v & 15};
 }
 
-void set_tuned_blocks_per_cu(int mode, int dim, int n, int blocks) {
-  if (mode < 0 || mode > 3 || dim < 2 || dim > 3 || n < 1 || n > 16) return;
-  g_blocks_per_cu[mode][dim - 2][n].store(blocks < 0 ? 0 : blocks, std::memory_order_relaxed);
+int set_launch_shape(int mode, int dim, int n, int blocks_per_cu, int variant) {
+  init_shapes();
+  if (mode < 0 || mode > 3) return -1;
+  if (dim < 2 || dim > 3) return -2;
+  if (n < 1 || n > 16) return -3;
+  if (blocks_per_cu < -1 || blocks_per_cu > 64) return -4;
+  if (variant < 0 || variant > (dim == 3 ? 3 : 2)) return -5;
+  g_shape[mode][dim - 2][n].store(blocks_per_cu < 0 ? -1 : blocks_per_cu * 16 + variant, std::memory_order_relaxed);
+  return 0;
 }
 
 }  // namespace kron
@@ -177,5 +207,21 @@ const char* kron_status_string(int status) {
 }
 
 const char* kron_version(void) { return "kron 0.1 gfx950"; }
+
+int kron_set_launch(int mode, int dim, int n, int blocks_per_cu, int variant) {
+  return kron::set_launch_shape(mode, dim, n, blocks_per_cu, variant);
+}
+
+int kron_get_launch(int mode, int dim, int n, int* blocks_per_cu, int* variant) {
+  if (mode < 0 || mode > 3) return -1;
+  if (dim < 2 || dim > 3) return -2;
+  if (n < 1 || n > 16) return -3;
+  if (!blocks_per_cu) return -4;
+  if (!variant) return -5;
+  const kron::LaunchShape sh = kron::launch_shape(mode, dim, n);
+  *blocks_per_cu = sh.blocks_per_cu;
+  *variant = sh.variant;
+  return 0;
+}
 
 }  // extern "C"

@@ -184,7 +184,7 @@ struct Tile2D {
 
 // ---- 3-D tile ---------------------------------------------------------------------
 
-template <class M, int N, bool kVec, bool kTrans>
+template <class M, int N, bool kVec, bool kTrans, bool kContig = false>
 struct Tile3D {
   using io_t = typename M::io_t;
   using acc_t = typename M::acc_t;
@@ -192,10 +192,10 @@ struct Tile3D {
   static constexpr int Q = Geo<N>::Q;
   static constexpr int kOps = Q * Q * Q;
   static constexpr int E = N * N * N;
-  static constexpr bool kStoreVec = kVec && (M::drow(0, 1) == 1);
+  static constexpr bool kStoreVec = kVec && (kContig || M::drow(0, 1) == 1);
 
   fac_t fC, fA, fB;
-  AxisPart<N, E> pLi;   // load: slot L on the slow axis a
+  AxisPart<N, E> pLi;   // load: slot L on the slow axis a (kContig: on the middle axis b)
   AxisPart<N, E> pLo;   // store: slot L on the middle axis j
   int offI[4], opI[4];  // load: fast slots 4g + s
   bool vI[4];
@@ -203,13 +203,18 @@ struct Tile3D {
   bool vO[4];
 
   __device__ __forceinline__ Tile3D(const io_t* A, const io_t* B, const io_t* C, int L, int g)
-      : pLi(L, N * N, Q * Q), pLo(L, N, Q) {
+      : pLi(L, kContig ? N : N * N, kContig ? Q : Q * Q), pLo(L, N, Q) {
     fC = M::template load_fac<N, kTrans>(C, L, g, 0);
-    fA = M::template load_fac<N, kTrans>(A, L, g, 1);
-    fB = M::template load_fac<N, kTrans>(B, L, g, 0);
+    if constexpr (kContig) {
+      fB = M::template load_fac<N, kTrans>(B, L, g, 1);
+      fA = M::template load_fac<N, kTrans>(A, L, g, 0);
+    } else {
+      fA = M::template load_fac<N, kTrans>(A, L, g, 1);
+      fB = M::template load_fac<N, kTrans>(B, L, g, 0);
+    }
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-      AxisPart<N, E> pi(4 * g + s, 1, 1), po(M::drow(g, s), 1, 1);
+      AxisPart<N, E> pi(4 * g + s, 1, 1), po(kContig ? 4 * g + s : M::drow(g, s), 1, 1);
       offI[s] = pi.off; opI[s] = pi.op; vI[s] = pi.valid;
       offO[s] = po.off; opO[s] = po.op; vO[s] = po.valid;
     }
@@ -222,7 +227,8 @@ struct Tile3D {
   __device__ __forceinline__ void load(const io_t* Xt, int64_t rem, acc_t (&t)[16], int only = -1) const {
 #pragma unroll
     for (int b = 0; b < 16; ++b) {
-      AxisPart<N, E> pS(b, N, Q);  // slab on the middle axis
+      // slab on the middle axis (kContig: on the slow axis)
+      AxisPart<N, E> pS(b, kContig ? N * N : N, kContig ? Q * Q : Q);
       if constexpr (N == 16 && kVec) {
         t[b] = Mem<io_t>::load4(Xt + pLi.off + pS.off + offI[0]);
       } else if constexpr (kVec) {
@@ -239,30 +245,55 @@ struct Tile3D {
     }
   }
 
+  // After exchange_groups_slabs, the value for output slab `o` and
+  // contraction slots 4g + s sits in register [4 * g_old + s][r_old] where
+  // (g_old, r_old) held row o before the exchange.
+  __device__ __forceinline__ static void regather(const acc_t (&t)[16], int o, acc_t& z) {
+    int gi = 0, ri = 0;
+#pragma unroll
+    for (int gg = 0; gg < 4; ++gg)
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr)
+        if (M::drow(gg, rr) == o) { gi = gg; ri = rr; }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) z[s] = t[4 * gi + s][ri];
+  }
+
   // t: loaded slabs in, results (slab i) out
   __device__ __forceinline__ void compute(acc_t (&t)[16]) const {
+    if constexpr (kContig) {
+      // load held X(a = slab, b = slot L, c = slots 4g+s)
 #pragma unroll
-    for (int b = 0; b < 16; ++b) t[b] = M::da_in(fC, t[b]);
+      for (int a = 0; a < 16; ++a) t[a] = M::da_in(fC, t[a]);   // contract c: rows b, column k
 #pragma unroll
-    for (int b = 0; b < 16; ++b) t[b] = M::db(fA, t[b]);
-    exchange_groups_slabs(t);
-    acc_t y[16];
+      for (int a = 0; a < 16; ++a) t[a] = M::da(fB, t[a]);      // contract b: rows k, column j
+      exchange_groups_slabs(t);                                  // -> slab k, slots a on (g, s)
+      acc_t u[16];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      // row i was held by lane group gi, register ri before the exchange
-      int gi = 0, ri = 0;
+      for (int k = 0; k < 16; ++k) {
+        acc_t z;
+        regather(t, k, z);
+        u[k] = M::db(fA, z);                                     // contract a: rows i, column j
+      }
+      exchange_groups_slabs(u);                                  // -> slab i, slots k on (g, s)
 #pragma unroll
-      for (int gg = 0; gg < 4; ++gg)
+      for (int i = 0; i < 16; ++i) regather(u, i, t[i]);
+    } else {
 #pragma unroll
-        for (int rr = 0; rr < 4; ++rr)
-          if (M::drow(gg, rr) == i) { gi = gg; ri = rr; }
-      acc_t z;
+      for (int b = 0; b < 16; ++b) t[b] = M::da_in(fC, t[b]);
 #pragma unroll
-      for (int s = 0; s < 4; ++s) z[s] = t[4 * gi + s][ri];
-      y[i] = M::da(fB, z);
+      for (int b = 0; b < 16; ++b) t[b] = M::db(fA, t[b]);
+      exchange_groups_slabs(t);
+      acc_t y[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        acc_t z;
+        regather(t, i, z);
+        y[i] = M::da(fB, z);
+      }
+#pragma unroll
+      for (int i = 0; i < 16; ++i) t[i] = y[i];
     }
-#pragma unroll
-    for (int i = 0; i < 16; ++i) t[i] = y[i];
   }
 
   __device__ __forceinline__ void store(io_t* Yt, int64_t rem, const acc_t (&t)[16], int only = -1) const {
@@ -341,24 +372,43 @@ __global__ __launch_bounds__(kBlock) void kron2d_kernel(const typename M::io_t* 
   }
 }
 
-template <class M, int N, bool kVec, bool kTrans>
+// kPipe: the loads of a wavefront's next tile are issued before the current
+// tile is computed, so every wavefront keeps a tile of HBM reads in flight.
+template <class M, int N, bool kVec, bool kTrans, bool kPipe, bool kContig>
 __global__ __launch_bounds__(kBlock) void kron3d_kernel(const typename M::io_t* __restrict__ A,
                                                         const typename M::io_t* __restrict__ B,
                                                         const typename M::io_t* __restrict__ C,
                                                         const typename M::io_t* __restrict__ X,
                                                         typename M::io_t* __restrict__ Y, int64_t batch,
                                                         int64_t ntiles) {
-  using T = Tile3D<M, N, kVec, kTrans>;
+  using T = Tile3D<M, N, kVec, kTrans, kContig>;
   using acc_t = typename M::acc_t;
+  constexpr int64_t kStep = (int64_t)T::kOps * T::E;
   const int l = threadIdx.x & 63, L = l & 15, g = l >> 4;
   const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * kBlock) >> 6;
   const T tile(A, B, C, L, g);
-  for (int64_t t = wave; t < ntiles; t += nwaves) {
-    acc_t v[16];
-    tile.load(X + t * T::kOps * T::E, batch - t * T::kOps, v);
-    tile.compute(v);
-    tile.finish(X + t * T::kOps * T::E, Y + t * T::kOps * T::E, batch - t * T::kOps, v);
+  if constexpr (kPipe) {
+    int64_t t = wave;
+    if (t >= ntiles) return;
+    acc_t cur[16];
+    tile.load(X + t * kStep, batch - t * T::kOps, cur);
+    for (; t < ntiles; t += nwaves) {
+      const int64_t tn = t + nwaves;
+      acc_t nxt[16];
+      if (tn < ntiles) tile.load(X + tn * kStep, batch - tn * T::kOps, nxt);
+      tile.compute(cur);
+      tile.finish(X + t * kStep, Y + t * kStep, batch - t * T::kOps, cur);
+#pragma unroll
+      for (int i = 0; i < 16; ++i) cur[i] = nxt[i];
+    }
+  } else {
+    for (int64_t t = wave; t < ntiles; t += nwaves) {
+      acc_t v[16];
+      tile.load(X + t * kStep, batch - t * T::kOps, v);
+      tile.compute(v);
+      tile.finish(X + t * kStep, Y + t * kStep, batch - t * T::kOps, v);
+    }
   }
 }
 

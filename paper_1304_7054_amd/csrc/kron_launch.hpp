@@ -41,48 +41,92 @@ inline unsigned grid_blocks(int64_t waves_needed, int occ, int per_cu) {
 
 inline bool aligned_to(const void* p, int bytes) { return (reinterpret_cast<uintptr_t>(p) % bytes) == 0; }
 
-constexpr int k2dTiles = 4;
+template <class M, int N, bool kTrans, bool kVec, int kTiles>
+void launch2d_k(const typename M::io_t* A, const typename M::io_t* B, const typename M::io_t* X,
+                typename M::io_t* Y, int64_t batch, int64_t ntiles, int per_cu, hipStream_t stream) {
+  auto k = kron2d_kernel<M, N, kVec, kTrans, kTiles>;
+  const int64_t waves = (ntiles + kTiles - 1) / kTiles;
+  hipLaunchKernelGGL(k, dim3(grid_blocks(waves, occupancy_blocks(k), per_cu)), dim3(kBlock), 0, stream, A, B, X, Y,
+                     batch, ntiles);
+}
 
+template <class M, int N, bool kTrans, bool kVec>
+void launch2d_v(int variant, const typename M::io_t* A, const typename M::io_t* B, const typename M::io_t* X,
+                typename M::io_t* Y, int64_t batch, int64_t ntiles, int per_cu, hipStream_t stream) {
+  switch (variant) {
+    case 1:
+      launch2d_k<M, N, kTrans, kVec, 8>(A, B, X, Y, batch, ntiles, per_cu, stream);
+      break;
+    case 2:
+      launch2d_k<M, N, kTrans, kVec, 2>(A, B, X, Y, batch, ntiles, per_cu, stream);
+      break;
+    default:
+      launch2d_k<M, N, kTrans, kVec, 4>(A, B, X, Y, batch, ntiles, per_cu, stream);
+  }
+}
+
+// 2-D variants: tiles kept in flight per wavefront, 0 -> 4, 1 -> 8, 2 -> 2.
 template <class M, int N, bool kTrans>
 int launch2d_n(const typename M::io_t* A, const typename M::io_t* B, const typename M::io_t* X,
                typename M::io_t* Y, int64_t batch, hipStream_t stream, int mode) {
   using io_t = typename M::io_t;
   constexpr int64_t ops = (int64_t)Geo<N>::Q * Geo<N>::Q;
   const int64_t ntiles = (batch + ops - 1) / ops;
-  const int64_t waves = (ntiles + k2dTiles - 1) / k2dTiles;
-  const int per_cu = tuned_blocks_per_cu(mode, 2, N);
+  const LaunchShape sh = launch_shape(mode, 2, N);
   if constexpr (Geo<N>::kVec) {
     if (aligned_to(X, Mem<io_t>::kAlign) && aligned_to(Y, Mem<io_t>::kAlign)) {
-      auto k = kron2d_kernel<M, N, true, kTrans, k2dTiles>;
-      hipLaunchKernelGGL(k, dim3(grid_blocks(waves, occupancy_blocks(k), per_cu)), dim3(kBlock), 0, stream, A, B,
-                         X, Y, batch, ntiles);
+      launch2d_v<M, N, kTrans, true>(sh.variant, A, B, X, Y, batch, ntiles, sh.blocks_per_cu, stream);
       return 0;
     }
   }
-  auto k = kron2d_kernel<M, N, false, kTrans, k2dTiles>;
-  hipLaunchKernelGGL(k, dim3(grid_blocks(waves, occupancy_blocks(k), per_cu)), dim3(kBlock), 0, stream, A, B, X, Y,
-                     batch, ntiles);
+  launch2d_v<M, N, kTrans, false>(sh.variant, A, B, X, Y, batch, ntiles, sh.blocks_per_cu, stream);
   return 0;
 }
 
+template <class M, int N, bool kTrans, bool kVec, bool kPipe, bool kContig>
+void launch3d_k(const typename M::io_t* A, const typename M::io_t* B, const typename M::io_t* C,
+                const typename M::io_t* X, typename M::io_t* Y, int64_t batch, int64_t ntiles, int per_cu,
+                hipStream_t stream) {
+  auto k = kron3d_kernel<M, N, kVec, kTrans, kPipe, kContig>;
+  hipLaunchKernelGGL(k, dim3(grid_blocks(ntiles, occupancy_blocks(k), per_cu)), dim3(kBlock), 0, stream, A, B, C, X,
+                     Y, batch, ntiles);
+}
+
+template <class M, int N, bool kTrans, bool kVec>
+void launch3d_v(int variant, const typename M::io_t* A, const typename M::io_t* B, const typename M::io_t* C,
+                const typename M::io_t* X, typename M::io_t* Y, int64_t batch, int64_t ntiles, int per_cu,
+                hipStream_t stream) {
+  switch (variant) {
+    case 1:
+      launch3d_k<M, N, kTrans, kVec, true, false>(A, B, C, X, Y, batch, ntiles, per_cu, stream);
+      break;
+    case 2:
+      launch3d_k<M, N, kTrans, kVec, false, true>(A, B, C, X, Y, batch, ntiles, per_cu, stream);
+      break;
+    case 3:
+      launch3d_k<M, N, kTrans, kVec, true, true>(A, B, C, X, Y, batch, ntiles, per_cu, stream);
+      break;
+    default:
+      launch3d_k<M, N, kTrans, kVec, false, false>(A, B, C, X, Y, batch, ntiles, per_cu, stream);
+  }
+}
+
+// 3-D variants: bit 0 = next tile prefetched, bit 1 = contiguous loads
+// (operand slabs along the slow axis, a second lane-group exchange).
 template <class M, int N, bool kTrans>
 int launch3d_n(const typename M::io_t* A, const typename M::io_t* B, const typename M::io_t* C,
                const typename M::io_t* X, typename M::io_t* Y, int64_t batch, hipStream_t stream, int mode) {
   using io_t = typename M::io_t;
   constexpr int64_t ops = (int64_t)Geo<N>::Q * Geo<N>::Q * Geo<N>::Q;
   const int64_t ntiles = (batch + ops - 1) / ops;
-  const int per_cu = tuned_blocks_per_cu(mode, 3, N);
+  const LaunchShape sh = launch_shape(mode, 3, N);
   if constexpr (Geo<N>::kVec) {
     if (aligned_to(X, Mem<io_t>::kAlign) && aligned_to(Y, Mem<io_t>::kAlign)) {
-      auto k = kron3d_kernel<M, N, true, kTrans>;
-      hipLaunchKernelGGL(k, dim3(grid_blocks(ntiles, occupancy_blocks(k), per_cu)), dim3(kBlock), 0, stream, A, B,
-                         C, X, Y, batch, ntiles);
+      launch3d_v<M, N, kTrans, true>(sh.variant, A, B, C, X, Y, batch, ntiles, sh.blocks_per_cu, stream);
       return 0;
     }
   }
-  auto k = kron3d_kernel<M, N, false, kTrans>;
-  hipLaunchKernelGGL(k, dim3(grid_blocks(ntiles, occupancy_blocks(k), per_cu)), dim3(kBlock), 0, stream, A, B, C,
-                     X, Y, batch, ntiles);
+  launch3d_v<M, N, kTrans, false>(sh.variant, A, B, C, X, Y, batch, ntiles, sh.blocks_per_cu, stream);
   return 0;
 }
 

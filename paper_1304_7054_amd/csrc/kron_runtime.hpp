@@ -11,10 +11,15 @@ namespace kron {
 // Compute units of the current device (cached per device ordinal).
 int device_cus();
 
-// Workgroups per CU chosen by the autotuner for (mode, dim, n); 0 = the
-// kernel's occupancy limit.
-int tuned_blocks_per_cu(int mode, int dim, int n);
-void set_tuned_blocks_per_cu(int mode, int dim, int n, int blocks);
+// Launch shape for (mode, dim, n): workgroups per CU (0 = as many as are
+// resident at once) and kernel variant.  Defaults come from a table measured
+// on MI355X; kron_set_launch / kron_autotune replace them.
+struct LaunchShape {
+  int blocks_per_cu;
+  int variant;
+};
+LaunchShape launch_shape(int mode, int dim, int n);
+int set_launch_shape(int mode, int dim, int n, int blocks_per_cu, int variant);
 
 // Forward launches of each precision mode, defined in kron_<mode>.hip.
 // Return 0, or -1 for an n outside 1..16.
