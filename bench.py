@@ -38,6 +38,9 @@ def parse():
     p.add_argument("--warmup", type=int, default=5)
     p.add_argument("--only-headline", action="store_true", help="skip the other modes")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    p.add_argument("--copy-calibration", action="store_true",
+                   help="first run three plain 1 GiB device copies (a kernel of known traffic for "
+                        "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)")
     return p.parse_args()
 
 
@@ -188,6 +191,14 @@ def main():
     kron.lib()  # fail loudly if the HIP library is missing
     import workloads
 
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        torch.cuda.empty_cache()
     head = measure(torch, "f32", 3, 16, workloads.BATCH_3D[16], args.steps, args.warmup, seed=2)
     others = []
     if not args.only_headline:

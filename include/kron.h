@@ -112,6 +112,39 @@ int kron2d_batched_adjoint_f64(int n, const double* A, const double* B, const do
 int kron3d_batched_adjoint_f64(int n, const double* A, const double* B, const double* C,
                                const double* X, double* Y, int64_t batch, hipStream_t stream);
 
+/* ---- backward ---------------------------------------------------------------- */
+
+/* Gradients of L = sum_p <dY_p, Y_p> for the forward actions above (the
+   shared factors enter every operand, so their gradients are summed over the
+   batch; the paper's transpose-once remark of Section 2.2 gives dX as the
+   transposed action):
+     2-D: dX_p = B^T dY_p A,  dA = sum_p dY_p^T (B X_p),  dB = sum_p dY_p A X_p^T
+     3-D: dX = (A^T (x) B^T (x) C^T) dY;  in operand indices (element (a, b, c)
+          at a*n^2 + b*n + c):
+          dA(i, a) = sum_p sum_{j,k} dY(i, j, k) sum_{b,c} B(j, b) C(k, c) X(a, b, c)
+          and likewise dB over (i, k), dC over (i, j).
+   Layouts as in the forward calls; dA, dB, dC are n x n column-major and are
+   overwritten (zero for batch == 0).  Any of dX, dA, dB, dC may be NULL to
+   skip it; X may be NULL when only dX is wanted.  dX must not alias X or dY.
+   `ws` is caller-owned device memory of at least
+   kron_backward_workspace_size(dim, n, batch, mode) bytes (per-wavefront
+   partial sums; needed only for dA/dB/dC).  The summation order is fixed, so
+   repeated calls on the same device give identical bits.  FP32 partial sums,
+   final sums in FP64.  Asynchronous on `stream`. */
+size_t kron_backward_workspace_size(int dim, int n, int64_t batch, int mode);
+int kron2d_backward_f32(int n, const float* A, const float* B, const float* X, const float* dY,
+                        float* dX, float* dA, float* dB, int64_t batch, void* ws, size_t ws_bytes,
+                        hipStream_t stream);
+int kron3d_backward_f32(int n, const float* A, const float* B, const float* C, const float* X,
+                        const float* dY, float* dX, float* dA, float* dB, float* dC, int64_t batch,
+                        void* ws, size_t ws_bytes, hipStream_t stream);
+int kron2d_backward_f64(int n, const double* A, const double* B, const double* X, const double* dY,
+                        double* dX, double* dA, double* dB, int64_t batch, void* ws, size_t ws_bytes,
+                        hipStream_t stream);
+int kron3d_backward_f64(int n, const double* A, const double* B, const double* C, const double* X,
+                        const double* dY, double* dX, double* dA, double* dB, double* dC, int64_t batch,
+                        void* ws, size_t ws_bytes, hipStream_t stream);
+
 /* ---- launch shape ----------------------------------------------------------- */
 
 /* How the kernels for (mode, dim, n) are launched: `blocks_per_cu` 256-thread

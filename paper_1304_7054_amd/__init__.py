@@ -12,6 +12,11 @@ from ._binding import (  # noqa: F401
     MODE_F32,
     MODE_F64,
     SIGNATURES,
+    kron2d_backward_f32,
+    kron2d_backward_f64,
+    kron3d_backward_f32,
+    kron3d_backward_f64,
+    kron_backward_workspace_size,
     kron2d_batched_adjoint_f32,
     kron2d_batched_adjoint_f64,
     kron2d_batched_bf16,

@@ -28,7 +28,7 @@ class KronError(RuntimeError):
 
 _LIB = None
 
-# (name, argument kinds); 'i' int, 'l' int64, 'p' pointer, 's' stream, 'z' size_t
+# (name, argument kinds); 'i' int, 'l' int64, 'p' pointer, 'S' stream, 'z' size_t
 SIGNATURES = {
     "kron2d_batched_f32": "ipppplS",
     "kron2d_batched_f64": "ipppplS",
@@ -42,6 +42,10 @@ SIGNATURES = {
     "kron3d_batched_adjoint_f32": "ippppplS",
     "kron2d_batched_adjoint_f64": "ipppplS",
     "kron3d_batched_adjoint_f64": "ippppplS",
+    "kron2d_backward_f32": "ippppppplpzS",
+    "kron3d_backward_f32": "ippppppppplpzS",
+    "kron2d_backward_f64": "ippppppplpzS",
+    "kron3d_backward_f64": "ippppppppplpzS",
 }
 
 _CT = {"i": ctypes.c_int, "l": ctypes.c_int64, "p": ctypes.c_void_p, "S": ctypes.c_void_p,
@@ -64,6 +68,8 @@ def lib():
         L.kron_status_string.restype = ctypes.c_char_p
         L.kron_version.argtypes = []
         L.kron_version.restype = ctypes.c_char_p
+        L.kron_backward_workspace_size.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int]
+        L.kron_backward_workspace_size.restype = ctypes.c_size_t
         L.kron_set_launch.argtypes = [ctypes.c_int] * 5
         L.kron_set_launch.restype = ctypes.c_int
         L.kron_get_launch.argtypes = [ctypes.c_int] * 3 + [ctypes.POINTER(ctypes.c_int)] * 2
@@ -188,3 +194,52 @@ def kron2d_batched_adjoint_f64(n, A, B, X, Y, batch, stream=None):
 
 def kron3d_batched_adjoint_f64(n, A, B, C, X, Y, batch, stream=None):
     return _dim_call("kron3d_batched_adjoint_f64", 3, torch.float64, n, (A, B, C), X, Y, batch, stream)
+
+
+def kron_backward_workspace_size(dim, n, batch, mode):
+    """Bytes of device workspace the factor gradients need."""
+    return int(lib().kron_backward_workspace_size(int(dim), int(n), int(batch), int(mode)))
+
+
+def _backward_call(name, dim, dtype, mode, n, mats, X, dY, dX, grads, batch, ws, stream):
+    n, batch = int(n), int(batch)
+    if not 1 <= n <= 16:
+        raise ValueError(f"n must be in 1..16, got {n}")
+    if batch < 0:
+        raise ValueError("batch must be >= 0")
+    size = batch * n ** dim
+    pm = [_arr(M, dtype, n * n, f"factor {i}") for i, M in enumerate(mats)]
+    px = _arr(X, dtype, size, "X")
+    pdy = _arr(dY, dtype, size, "dY")
+    pdx = _arr(dX, dtype, size, "dX")
+    pg = [_arr(G, dtype, n * n, f"gradient {i}") for i, G in enumerate(grads)]
+    for t in [dX] + list(grads):
+        if t is not None and size > 0 and any(o is not None and t.data_ptr() == o.data_ptr() for o in (X, dY)):
+            raise ValueError("outputs must not alias X or dY")
+    need = kron_backward_workspace_size(dim, n, batch, mode) if any(G is not None for G in grads) else 0
+    if need and (ws is None or ws.numel() * ws.element_size() < need):
+        raise ValueError(f"workspace must hold {need} bytes")
+    pws = ctypes.c_void_p(ws.data_ptr()) if ws is not None else None
+    nbytes = ws.numel() * ws.element_size() if ws is not None else 0
+    return _call(name, n, *pm, px, pdy, pdx, *pg, batch, pws, nbytes, _stream(stream))
+
+
+def kron2d_backward_f32(n, A, B, X, dY, dX, dA, dB, batch, ws=None, stream=None):
+    """dX, dA, dB of L = sum_p <dY_p, Y_p> (see include/kron.h); None skips an output."""
+    return _backward_call("kron2d_backward_f32", 2, torch.float32, MODE_F32, n, (A, B), X, dY, dX, (dA, dB),
+                          batch, ws, stream)
+
+
+def kron3d_backward_f32(n, A, B, C, X, dY, dX, dA, dB, dC, batch, ws=None, stream=None):
+    return _backward_call("kron3d_backward_f32", 3, torch.float32, MODE_F32, n, (A, B, C), X, dY, dX,
+                          (dA, dB, dC), batch, ws, stream)
+
+
+def kron2d_backward_f64(n, A, B, X, dY, dX, dA, dB, batch, ws=None, stream=None):
+    return _backward_call("kron2d_backward_f64", 2, torch.float64, MODE_F64, n, (A, B), X, dY, dX, (dA, dB),
+                          batch, ws, stream)
+
+
+def kron3d_backward_f64(n, A, B, C, X, dY, dX, dA, dB, dC, batch, ws=None, stream=None):
+    return _backward_call("kron3d_backward_f64", 3, torch.float64, MODE_F64, n, (A, B, C), X, dY, dX,
+                          (dA, dB, dC), batch, ws, stream)

@@ -27,8 +27,23 @@ def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
+def _obj(src):
+    return os.path.join(OBJ_DIR, os.path.basename(src)[:-4] + ".o")
+
+
+def _stale(src):
+    """An object is stale when older than its source or any shared header."""
+    obj = _obj(src)
+    if not os.path.exists(obj):
+        return True
+    deps = [src, os.path.join(INCLUDE, "kron.h")]
+    deps += [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hpp")]
+    t = os.path.getmtime(obj)
+    return any(os.path.getmtime(d) > t for d in deps)
+
+
 def _compile(src, verbose):
-    obj = os.path.join(OBJ_DIR, os.path.basename(src)[:-4] + ".o")
+    obj = _obj(src)
     cmd = [HIPCC, *COMMON, "-c", src, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
@@ -42,13 +57,21 @@ def _compile(src, verbose):
     return obj
 
 
-def build(verbose: bool = False, jobs: int = 0) -> str:
-    """Compile every HIP source and link libkron.so; returns the library path."""
+def build(verbose: bool = False, jobs: int = 0, force: bool = True) -> str:
+    """Compile the HIP sources (all of them, or with force=False only those
+    whose object is out of date) and link libkron.so; returns its path."""
     os.makedirs(OBJ_DIR, exist_ok=True)
     srcs = sources()
-    jobs = jobs or min(len(srcs), max(1, min(16, os.cpu_count() or 1)))
-    with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), srcs))
+    keep = {os.path.basename(_obj(s)) for s in srcs}
+    for f in os.listdir(OBJ_DIR):
+        if f.endswith(".o") and f not in keep:
+            os.remove(os.path.join(OBJ_DIR, f))
+    todo = [s for s in srcs if force or _stale(s)]
+    if todo:
+        jobs = jobs or min(len(todo), max(1, min(16, os.cpu_count() or 1)))
+        with cf.ThreadPoolExecutor(jobs) as ex:
+            list(ex.map(lambda s: _compile(s, verbose), todo))
+    objs = [_obj(s) for s in srcs]
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     if verbose:
@@ -59,4 +82,4 @@ def build(verbose: bool = False, jobs: int = 0) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, force="--incremental" not in sys.argv))

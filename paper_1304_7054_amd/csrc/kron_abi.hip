@@ -42,11 +42,18 @@ void init_shapes() {
   (void)done;
 }
 
-// Built-in defaults, measured on MI355X (see the autotuner for the search).
+// Built-in defaults, measured on MI355X at n = 16 with 1 GiB batches (the
+// autotuner refines them per n).
 LaunchShape default_shape(int mode, int dim, int n) {
-  (void)mode;
   (void)n;
-  if (dim == 3) return LaunchShape{0, 1};
+  if (dim == 3) {
+    switch (mode) {
+      case 0: return LaunchShape{0, 4};  // FP32: contiguous rows, 2-slab window
+      case 1: return LaunchShape{0, 3};  // FP64: contiguous rows, next tile prefetched
+      case 2: return LaunchShape{2, 5};  // bf16x3: 4-slab window, 2 workgroups per CU
+      default: return LaunchShape{0, 5}; // bf16 storage: 4-slab window
+    }
+  }
   return LaunchShape{0, 0};
 }
 }  // namespace
@@ -65,9 +72,26 @@ int set_launch_shape(int mode, int dim, int n, int blocks_per_cu, int variant) {
   if (dim < 2 || dim > 3) return -2;
   if (n < 1 || n > 16) return -3;
   if (blocks_per_cu < -1 || blocks_per_cu > 64) return -4;
-  if (variant < 0 || variant > (dim == 3 ? 3 : 2)) return -5;
+  if (variant < 0 || variant > (dim == 3 ? 7 : 2)) return -5;
   g_shape[mode][dim - 2][n].store(blocks_per_cu < 0 ? -1 : blocks_per_cu * 16 + variant, std::memory_order_relaxed);
   return 0;
+}
+
+int fwd3d_f32(int n, const float* A, const float* B, const float* C, const float* X, float* Y, int64_t batch,
+              hipStream_t s, bool trans) {
+  return n <= 8 ? fwd3d_f32_lo(n, A, B, C, X, Y, batch, s, trans) : fwd3d_f32_hi(n, A, B, C, X, Y, batch, s, trans);
+}
+int fwd3d_f64(int n, const double* A, const double* B, const double* C, const double* X, double* Y,
+              int64_t batch, hipStream_t s, bool trans) {
+  return n <= 8 ? fwd3d_f64_lo(n, A, B, C, X, Y, batch, s, trans) : fwd3d_f64_hi(n, A, B, C, X, Y, batch, s, trans);
+}
+int fwd3d_bf16x3(int n, const float* A, const float* B, const float* C, const float* X, float* Y, int64_t batch,
+                 hipStream_t s) {
+  return n <= 8 ? fwd3d_bf16x3_lo(n, A, B, C, X, Y, batch, s) : fwd3d_bf16x3_hi(n, A, B, C, X, Y, batch, s);
+}
+int fwd3d_bf16(int n, const uint16_t* A, const uint16_t* B, const uint16_t* C, const uint16_t* X, uint16_t* Y,
+               int64_t batch, hipStream_t s) {
+  return n <= 8 ? fwd3d_bf16_lo(n, A, B, C, X, Y, batch, s) : fwd3d_bf16_hi(n, A, B, C, X, Y, batch, s);
 }
 
 }  // namespace kron
@@ -101,6 +125,27 @@ int check3d(int n, const void* A, const void* B, const void* C, const void* X, c
   if (!X) return -5;
   if (!Y || Y == X) return -6;
   if (batch < 0) return -7;
+  return 0;
+}
+
+}  // namespace
+
+namespace {
+
+// Shared checks of the backward entry points.  k0 is the position of X.
+template <typename T>
+int check_backward(int dim, int n, const T* X, const T* dY, const T* dX, const void* gA, const void* gB,
+                   const void* gC, int64_t batch, const void* ws, size_t ws_bytes, int k0) {
+  const bool factors = gA || gB || gC;
+  if (factors && !X && batch > 0) return -k0;
+  if (!dY && batch > 0) return -(k0 + 1);
+  if (dX && (dX == dY || dX == X)) return -(k0 + 2);
+  const int kb = k0 + 3 + dim;  // position of batch
+  if (batch < 0) return -kb;
+  if (factors && batch > 0) {
+    if (!ws) return -(kb + 1);
+    if (ws_bytes < kron::grad_workspace_bytes(dim, n, batch, (int)sizeof(T))) return -(kb + 2);
+  }
   return 0;
 }
 
@@ -190,6 +235,69 @@ int kron3d_batched_adjoint_f64(int n, const double* A, const double* B, const do
   if (int rc = check3d(n, A, B, C, X, Y, batch)) return rc;
   if (batch == 0) return 0;
   return finish_launch(kron::fwd3d_f64(n, A, B, C, X, Y, batch, stream, true));
+}
+
+size_t kron_backward_workspace_size(int dim, int n, int64_t batch, int mode) {
+  if ((dim != 2 && dim != 3) || n < 1 || n > KRON_MAX_N || batch < 0) return 0;
+  if (mode != KRON_MODE_F32 && mode != KRON_MODE_F64) return 0;
+  return kron::grad_workspace_bytes(dim, n, batch, mode == KRON_MODE_F64 ? 8 : 4);
+}
+
+
+int kron2d_backward_f32(int n, const float* A, const float* B, const float* X, const float* dY, float* dX,
+                        float* dA, float* dB, int64_t batch, void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (n < 1 || n > KRON_MAX_N) return -1;
+  if (!A) return -2;
+  if (!B) return -3;
+  if (int rc = check_backward<float>(2, n, X, dY, dX, dA, dB, nullptr, batch, ws, ws_bytes, 4)) return rc;
+  if (dX && batch > 0) {
+    if (int rc = finish_launch(kron::fwd2d_f32(n, A, B, dY, dX, batch, stream, true))) return rc;
+  }
+  if (dA || dB) return finish_launch(kron::grad2d_f32(n, A, B, X, dY, dA, dB, batch, ws, stream));
+  return 0;
+}
+
+int kron3d_backward_f32(int n, const float* A, const float* B, const float* C, const float* X, const float* dY,
+                        float* dX, float* dA, float* dB, float* dC, int64_t batch, void* ws, size_t ws_bytes,
+                        hipStream_t stream) {
+  if (n < 1 || n > KRON_MAX_N) return -1;
+  if (!A) return -2;
+  if (!B) return -3;
+  if (!C) return -4;
+  if (int rc = check_backward<float>(3, n, X, dY, dX, dA, dB, dC, batch, ws, ws_bytes, 5)) return rc;
+  if (dX && batch > 0) {
+    if (int rc = finish_launch(kron::fwd3d_f32(n, A, B, C, dY, dX, batch, stream, true))) return rc;
+  }
+  if (dA || dB || dC) return finish_launch(kron::grad3d_f32(n, A, B, C, X, dY, dA, dB, dC, batch, ws, stream));
+  return 0;
+}
+
+int kron2d_backward_f64(int n, const double* A, const double* B, const double* X, const double* dY, double* dX,
+                        double* dA, double* dB, int64_t batch, void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (n < 1 || n > KRON_MAX_N) return -1;
+  if (!A) return -2;
+  if (!B) return -3;
+  if (int rc = check_backward<double>(2, n, X, dY, dX, dA, dB, nullptr, batch, ws, ws_bytes, 4)) return rc;
+  if (dX && batch > 0) {
+    if (int rc = finish_launch(kron::fwd2d_f64(n, A, B, dY, dX, batch, stream, true))) return rc;
+  }
+  if (dA || dB) return finish_launch(kron::grad2d_f64(n, A, B, X, dY, dA, dB, batch, ws, stream));
+  return 0;
+}
+
+int kron3d_backward_f64(int n, const double* A, const double* B, const double* C, const double* X,
+                        const double* dY, double* dX, double* dA, double* dB, double* dC, int64_t batch, void* ws,
+                        size_t ws_bytes, hipStream_t stream) {
+  if (n < 1 || n > KRON_MAX_N) return -1;
+  if (!A) return -2;
+  if (!B) return -3;
+  if (!C) return -4;
+  if (int rc = check_backward<double>(3, n, X, dY, dX, dA, dB, dC, batch, ws, ws_bytes, 5)) return rc;
+  if (dX && batch > 0) {
+    if (int rc = finish_launch(kron::fwd3d_f64(n, A, B, C, dY, dX, batch, stream, true))) return rc;
+  }
+  if (dA || dB || dC) return finish_launch(kron::grad3d_f64(n, A, B, C, X, dY, dA, dB, dC, batch, ws, stream));
+  return 0;
 }
 
 const char* kron_status_string(int status) {

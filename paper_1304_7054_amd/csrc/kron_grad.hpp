@@ -1,0 +1,254 @@
+// Gradients of the batched Kronecker action with respect to the shared
+// factors, for L = sum_p <dY_p, Y_p>.
+//
+// 3-D (element (a, b, c) of an operand at a*n^2 + b*n + c, Y(i, j, k) =
+// sum A(i, a) B(j, b) C(k, c) X(a, b, c)):
+//   dA(i, a) = sum_p sum_{j,k} dY(i, j, k) U(a, j, k),  U = X with B on b and C on c
+//   dB(j, b) = sum_p sum_{i,k} dY(i, j, k) V(i, b, k),  V = X with A on a and C on c
+//   dC(k, c) = sum_p sum_{i,j} dY(i, j, k) W(i, j, c),  W = X with A on a and B on b
+// 2-D (X(u, v) at u*n + v, Y(i, j) = sum A(i, u) B(j, v) X(u, v)):
+//   dA(i, u) = sum_p sum_j dY(i, j) Z(u, j),  Z = X with B on v
+//   dB(j, v) = sum_p sum_i dY(i, j) W(i, v),  W = X with A on u
+// The paper folds transposes into the constant factors once (Section 2.2);
+// dX is the forward action with every factor transposed and runs on the
+// forward kernels.
+//
+// Per tile, each factor gradient is one more contraction on the matrix
+// cores: the two-factor product of X is formed in registers (two MFMA stages
+// and, in 3-D, one lane-group <-> slab exchange) in a layout whose row index
+// lines up with dY loaded in a matching layout, and the 16 x 16 product
+// dY * T^T accumulates across all tiles a wavefront visits.  Each wavefront
+// then writes its 16 x 16 partials; a second kernel sums them in a fixed
+// order (deterministic) and folds the diagonal blocks of packed tiles.
+#pragma once
+
+#include "kron_kernels.hpp"
+
+namespace kron {
+
+// Plain product of two data operands: acc += sum_s a[s] * b[s] on the
+// 16x16 instruction of the mode (FP32 or FP64 only).
+template <class M>
+__device__ __forceinline__ typename M::acc_t mma_data(const typename M::acc_t& a, const typename M::acc_t& b,
+                                                      typename M::acc_t acc);
+template <>
+__device__ __forceinline__ f32x4 mma_data<ModeF32>(const f32x4& a, const f32x4& b, f32x4 acc) {
+#pragma unroll
+  for (int s = 0; s < 4; ++s) acc = mfma_f32(a[s], b[s], acc);
+  return acc;
+}
+template <>
+__device__ __forceinline__ f64x4 mma_data<ModeF64>(const f64x4& a, const f64x4& b, f64x4 acc) {
+#pragma unroll
+  for (int s = 0; s < 4; ++s) acc = mfma_f64(a[s], b[s], acc);
+  return acc;
+}
+
+// Loads of a tile in an arbitrary axis assignment: memory axis `LAX` on the
+// lane index L, `GAX` on the row-group slots (kmap 0: 4g + s, 1: drow(g, s)),
+// `SAX` on the slab index.  Axes are 0 (slow, stride n^2), 1 (n), 2 (1).
+template <class M, int N, int Dim>
+struct GradLoader {
+  using io_t = typename M::io_t;
+  using acc_t = typename M::acc_t;
+  static constexpr int Q = Geo<N>::Q;
+  static constexpr int E = Dim == 3 ? N * N * N : N * N;
+  __device__ static constexpr int stride(int ax) { return Dim == 3 ? (ax == 0 ? N * N : ax == 1 ? N : 1) : (ax == 0 ? N : 1); }
+  __device__ static constexpr int opmul(int ax) { return Dim == 3 ? (ax == 0 ? Q * Q : ax == 1 ? Q : 1) : (ax == 0 ? Q : 1); }
+
+  int offL, opL, offG[4], opG[4];
+  bool vL, vG[4];
+
+  __device__ __forceinline__ GradLoader(int L, int g, int lax, int gax, int kmap) {
+    AxisPart<N, E> pl(L, stride(lax), opmul(lax));
+    offL = pl.off; opL = pl.op; vL = pl.valid;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      AxisPart<N, E> pg(kmap == 0 ? 4 * g + s : M::drow(g, s), stride(gax), opmul(gax));
+      offG[s] = pg.off; opG[s] = pg.op; vG[s] = pg.valid;
+    }
+  }
+
+  // one slab (sax < 0: no slab axis, 2-D)
+  __device__ __forceinline__ acc_t load(const io_t* P, int64_t rem, int slab, int sax) const {
+    int offS = 0, opS = 0;
+    bool vS = true;
+    if (sax >= 0) {
+      AxisPart<N, E> ps(slab, stride(sax), opmul(sax));
+      offS = ps.off; opS = ps.op; vS = ps.valid;
+    }
+    acc_t v;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const bool ok = vS && vL && vG[s] && (opL + opS + opG[s] < rem);
+      v[s] = ok ? P[offL + offS + offG[s]] : 0;
+    }
+    return v;
+  }
+};
+
+// Per-wavefront accumulation of the factor gradients over its tiles.
+// kWhich: bit 0 dA, bit 1 dB, bit 2 dC (3-D).
+template <class M, int N>
+struct Grad3D {
+  using io_t = typename M::io_t;
+  using acc_t = typename M::acc_t;
+  using fac_t = typename M::fac_t;
+  static constexpr int Q = Geo<N>::Q;
+  static constexpr int kOps = Q * Q * Q;
+  fac_t fA, fB, fC;  // Mt(L, 4g + s)
+  int L, g;
+
+  __device__ __forceinline__ Grad3D(const io_t* A, const io_t* B, const io_t* C, int L_, int g_) : L(L_), g(g_) {
+    fA = M::template load_fac<N, false>(A, L, g, 0);
+    fB = M::template load_fac<N, false>(B, L, g, 0);
+    fC = M::template load_fac<N, false>(C, L, g, 0);
+  }
+
+  // Contract the G index of t with factor f (data as MFMA operand B), per slab.
+  __device__ __forceinline__ void stage(const fac_t& f, acc_t (&t)[16]) const {
+#pragma unroll
+    for (int s = 0; s < 16; ++s) t[s] = M::db(f, t[s]);
+  }
+
+  // t: rows on (g, r) via drow, slabs s -> slabs = old rows, G slots 4g + s = old slabs
+  __device__ __forceinline__ static void swap_rows_slabs(acc_t (&t)[16]) {
+    exchange_groups_slabs(t);
+    acc_t u[16];
+#pragma unroll
+    for (int o = 0; o < 16; ++o) Tile3D<M, N, false, false>::regather(t, o, u[o]);
+#pragma unroll
+    for (int o = 0; o < 16; ++o) t[o] = u[o];
+  }
+
+  // acc += sum over slabs of dY(L-row, G) * T(G, L-col)
+  __device__ __forceinline__ static void contract(const acc_t (&dy)[16], const acc_t (&t)[16], acc_t& acc) {
+#pragma unroll
+    for (int s = 0; s < 16; ++s) acc = mma_data<M>(dy[s], t[s], acc);
+  }
+
+  // one gradient of one tile.  F = 0 (dA), 1 (dB), 2 (dC).
+  template <int F>
+  __device__ __forceinline__ void tile(const io_t* Xt, const io_t* dYt, int64_t rem, acc_t& acc) const {
+    // X layout: L = the factor's own axis, G = first contracted axis, S = second.
+    //   dA: L = a, G = c, S = b;  contract c with C, swap, contract b with B -> (G = j, L = a, S = k)
+    //   dB: L = b, G = c, S = a;  contract c with C, swap, contract a with A -> (G = i, L = b, S = k)
+    //   dC: L = c, G = b, S = a;  contract b with B, swap, contract a with A -> (G = i, L = c, S = j)
+    constexpr int lax = F;
+    constexpr int gax = F == 2 ? 1 : 2;
+    constexpr int sax = F == 0 ? 1 : 0;
+    GradLoader<M, N, 3> lx(L, g, lax, gax, 0);
+    acc_t t[16];
+#pragma unroll
+    for (int s = 0; s < 16; ++s) t[s] = lx.load(Xt, rem, s, sax);
+    stage(F == 2 ? fB : fC, t);
+    swap_rows_slabs(t);
+    stage(F == 0 ? fB : fA, t);
+    // dY layout: L = the factor's output index (same axis as `lax`), G = the
+    // row index just produced (drow slots), S = the remaining axis.
+    //   dA: L = i, G = j, S = k;  dB: L = j, G = i, S = k;  dC: L = k, G = i, S = j
+    constexpr int ygax = F == 0 ? 1 : 0;
+    constexpr int ysax = F == 2 ? 1 : 2;
+    GradLoader<M, N, 3> ly(L, g, lax, ygax, 1);
+    acc_t dy[16];
+#pragma unroll
+    for (int s = 0; s < 16; ++s) dy[s] = ly.load(dYt, rem, s, ysax);
+    contract(dy, t, acc);
+  }
+};
+
+template <class M, int N>
+struct Grad2D {
+  using io_t = typename M::io_t;
+  using acc_t = typename M::acc_t;
+  using fac_t = typename M::fac_t;
+  static constexpr int Q = Geo<N>::Q;
+  static constexpr int kOps = Q * Q;
+  fac_t fA, fB;
+  int L, g;
+
+  __device__ __forceinline__ Grad2D(const io_t* A, const io_t* B, int L_, int g_) : L(L_), g(g_) {
+    fA = M::template load_fac<N, false>(A, L, g, 0);
+    fB = M::template load_fac<N, false>(B, L, g, 0);
+  }
+
+  // F = 0 (dA): X (L = u, G = v), contract v with B -> (G = j, L = u); dY (L = i, G = j)
+  // F = 1 (dB): X (L = v, G = u), contract u with A -> (G = i, L = v); dY (L = j, G = i)
+  template <int F>
+  __device__ __forceinline__ void tile(const io_t* Xt, const io_t* dYt, int64_t rem, acc_t& acc) const {
+    constexpr int lax = F, gax = 1 - F;
+    GradLoader<M, N, 2> lx(L, g, lax, gax, 0);
+    acc_t t = M::db(F == 0 ? fB : fA, lx.load(Xt, rem, 0, -1));
+    GradLoader<M, N, 2> ly(L, g, lax, gax, 1);
+    acc = mma_data<M>(ly.load(dYt, rem, 0, -1), t, acc);
+  }
+};
+
+constexpr int kGradBlock = 256;
+
+// Partials: ws[(wave * 3 + f) * 256 + row * 16 + col] holds wavefront `wave`'s
+// 16 x 16 tile of factor f's gradient (row = drow(g, r), col = L).
+template <class M, int N, int Dim>
+__global__ __launch_bounds__(kGradBlock) void kron_grad_partial_kernel(
+    const typename M::io_t* __restrict__ A, const typename M::io_t* __restrict__ B,
+    const typename M::io_t* __restrict__ C, const typename M::io_t* __restrict__ X,
+    const typename M::io_t* __restrict__ dY, typename M::elem_t* __restrict__ ws, int64_t batch,
+    int64_t ntiles, int which) {
+  using acc_t = typename M::acc_t;
+  using T = typename M::elem_t;
+  const int l = threadIdx.x & 63, L = l & 15, g = l >> 4;
+  const int64_t wave = ((int64_t)blockIdx.x * kGradBlock + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * kGradBlock) >> 6;
+  acc_t acc[3];
+#pragma unroll
+  for (int f = 0; f < 3; ++f) acc[f] = acc_t{0, 0, 0, 0};
+  if constexpr (Dim == 3) {
+    using G3 = Grad3D<M, N>;
+    constexpr int64_t step = (int64_t)G3::kOps * N * N * N;
+    const G3 gr(A, B, C, L, g);
+    for (int64_t t = wave; t < ntiles; t += nwaves) {
+      const int64_t rem = batch - t * G3::kOps;
+      if (which & 1) gr.template tile<0>(X + t * step, dY + t * step, rem, acc[0]);
+      if (which & 2) gr.template tile<1>(X + t * step, dY + t * step, rem, acc[1]);
+      if (which & 4) gr.template tile<2>(X + t * step, dY + t * step, rem, acc[2]);
+    }
+  } else {
+    using G2 = Grad2D<M, N>;
+    constexpr int64_t step = (int64_t)G2::kOps * N * N;
+    const G2 gr(A, B, L, g);
+    for (int64_t t = wave; t < ntiles; t += nwaves) {
+      const int64_t rem = batch - t * G2::kOps;
+      if (which & 1) gr.template tile<0>(X + t * step, dY + t * step, rem, acc[0]);
+      if (which & 2) gr.template tile<1>(X + t * step, dY + t * step, rem, acc[1]);
+    }
+  }
+#pragma unroll
+  for (int f = 0; f < 3; ++f)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) ws[(wave * 3 + f) * 256 + M::drow(g, r) * 16 + L] = (T)acc[f][r];
+}
+
+// dM(i, j) = sum over wavefronts (in order) and over the Q diagonal blocks of
+// the partial tiles; one thread per entry of each requested factor; sums in
+// double.  Output column-major (i + n*j).
+template <typename io_t, typename T, int N>
+__global__ __launch_bounds__(kGradBlock) void kron_grad_reduce_kernel(const T* __restrict__ ws, int64_t nwaves,
+                                                                      io_t* __restrict__ dA, io_t* __restrict__ dB,
+                                                                      io_t* __restrict__ dC) {
+  constexpr int Q = Geo<N>::Q;
+  const int f = blockIdx.x;
+  io_t* out = f == 0 ? dA : f == 1 ? dB : dC;
+  if (out == nullptr) return;
+  for (int e = threadIdx.x; e < N * N; e += kGradBlock) {
+    const int i = e % N, j = e / N;
+    double s = 0.0;
+    for (int64_t w = 0; w < nwaves; ++w) {
+      const T* tile = ws + (w * 3 + f) * 256;
+#pragma unroll
+      for (int q = 0; q < Q; ++q) s += (double)tile[(q * N + i) * 16 + (q * N + j)];
+    }
+    out[i + N * j] = (io_t)s;
+  }
+}
+
+}  // namespace kron

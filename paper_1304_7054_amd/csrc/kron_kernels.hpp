@@ -224,25 +224,27 @@ struct Tile3D {
     return op < rem && (only < 0 || op == only);
   }
 
-  __device__ __forceinline__ void load(const io_t* Xt, int64_t rem, acc_t (&t)[16], int only = -1) const {
+  __device__ __forceinline__ void load_slab(const io_t* Xt, int64_t rem, int b, acc_t& v, int only = -1) const {
+    // slab on the middle axis (kContig: on the slow axis)
+    AxisPart<N, E> pS(b, kContig ? N * N : N, kContig ? Q * Q : Q);
+    if constexpr (N == 16 && kVec) {
+      v = Mem<io_t>::load4(Xt + pLi.off + pS.off + offI[0]);
+    } else if constexpr (kVec) {
+      bool ok = pS.valid && pLi.valid && vI[0] && take(pLi.op + pS.op + opI[0], rem, only);
+      if (ok) v = Mem<io_t>::load4(Xt + pLi.off + pS.off + offI[0]);
+      else v = acc_t{0, 0, 0, 0};
+    } else {
 #pragma unroll
-    for (int b = 0; b < 16; ++b) {
-      // slab on the middle axis (kContig: on the slow axis)
-      AxisPart<N, E> pS(b, kContig ? N * N : N, kContig ? Q * Q : Q);
-      if constexpr (N == 16 && kVec) {
-        t[b] = Mem<io_t>::load4(Xt + pLi.off + pS.off + offI[0]);
-      } else if constexpr (kVec) {
-        bool ok = pS.valid && pLi.valid && vI[0] && take(pLi.op + pS.op + opI[0], rem, only);
-        if (ok) t[b] = Mem<io_t>::load4(Xt + pLi.off + pS.off + offI[0]);
-        else t[b] = acc_t{0, 0, 0, 0};
-      } else {
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          bool ok = pS.valid && pLi.valid && vI[s] && take(pLi.op + pS.op + opI[s], rem, only);
-          t[b][s] = ok ? Mem<io_t>::load1(Xt + pLi.off + pS.off + offI[s]) : 0;
-        }
+      for (int s = 0; s < 4; ++s) {
+        bool ok = pS.valid && pLi.valid && vI[s] && take(pLi.op + pS.op + opI[s], rem, only);
+        v[s] = ok ? Mem<io_t>::load1(Xt + pLi.off + pS.off + offI[s]) : 0;
       }
     }
+  }
+
+  __device__ __forceinline__ void load(const io_t* Xt, int64_t rem, acc_t (&t)[16], int only = -1) const {
+#pragma unroll
+    for (int b = 0; b < 16; ++b) load_slab(Xt, rem, b, t[b], only);
   }
 
   // After exchange_groups_slabs, the value for output slab `o` and
@@ -259,59 +261,69 @@ struct Tile3D {
     for (int s = 0; s < 4; ++s) z[s] = t[4 * gi + s][ri];
   }
 
-  // t: loaded slabs in, results (slab i) out
-  __device__ __forceinline__ void compute(acc_t (&t)[16]) const {
+  // Stages 1 and 2 touch one slab at a time.
+  __device__ __forceinline__ void stage12(acc_t& v) const {
     if constexpr (kContig) {
-      // load held X(a = slab, b = slot L, c = slots 4g+s)
-#pragma unroll
-      for (int a = 0; a < 16; ++a) t[a] = M::da_in(fC, t[a]);   // contract c: rows b, column k
-#pragma unroll
-      for (int a = 0; a < 16; ++a) t[a] = M::da(fB, t[a]);      // contract b: rows k, column j
-      exchange_groups_slabs(t);                                  // -> slab k, slots a on (g, s)
-      acc_t u[16];
+      // slab a of X(a, b = slot L, c = slots 4g+s): contract c (rows b, column k), then b (rows k, column j)
+      v = M::da(fB, M::da_in(fC, v));
+    } else {
+      // slab b of X(a = slot L, b, c = slots 4g+s): contract c (rows a, column k), then a (rows i, column k)
+      v = M::db(fA, M::da_in(fC, v));
+    }
+  }
+
+  // The third mode needs every slab: exchange lane groups and slabs, contract,
+  // and (kContig) exchange back so that the result is stored in 1 KiB rows.
+  __device__ __forceinline__ void stage3(acc_t (&t)[16]) const {
+    exchange_groups_slabs(t);
+    acc_t u[16];
+    if constexpr (kContig) {
 #pragma unroll
       for (int k = 0; k < 16; ++k) {
         acc_t z;
         regather(t, k, z);
-        u[k] = M::db(fA, z);                                     // contract a: rows i, column j
+        u[k] = M::db(fA, z);          // contract a: rows i, column j, slab k
       }
-      exchange_groups_slabs(u);                                  // -> slab i, slots k on (g, s)
+      exchange_groups_slabs(u);       // -> slab i, slots k on (g, s)
 #pragma unroll
       for (int i = 0; i < 16; ++i) regather(u, i, t[i]);
     } else {
 #pragma unroll
-      for (int b = 0; b < 16; ++b) t[b] = M::da_in(fC, t[b]);
-#pragma unroll
-      for (int b = 0; b < 16; ++b) t[b] = M::db(fA, t[b]);
-      exchange_groups_slabs(t);
-      acc_t y[16];
-#pragma unroll
       for (int i = 0; i < 16; ++i) {
         acc_t z;
         regather(t, i, z);
-        y[i] = M::da(fB, z);
+        u[i] = M::da(fB, z);          // contract b: rows k, column j, slab i
       }
 #pragma unroll
-      for (int i = 0; i < 16; ++i) t[i] = y[i];
+      for (int i = 0; i < 16; ++i) t[i] = u[i];
+    }
+  }
+
+  // t: loaded slabs in, results (slab i) out
+  __device__ __forceinline__ void compute(acc_t (&t)[16]) const {
+#pragma unroll
+    for (int b = 0; b < 16; ++b) stage12(t[b]);
+    stage3(t);
+  }
+
+  __device__ __forceinline__ void store_slab(io_t* Yt, int64_t rem, int i, const acc_t& v, int only = -1) const {
+    AxisPart<N, E> pS(i, N * N, Q * Q);  // slab on the slow axis
+    if constexpr (N == 16 && kStoreVec) {
+      Mem<io_t>::store4(Yt + pS.off + pLo.off + offO[0], v);
+    } else if constexpr (kStoreVec) {
+      if (pS.valid && pLo.valid && vO[0] && take(pS.op + pLo.op + opO[0], rem, only))
+        Mem<io_t>::store4(Yt + pS.off + pLo.off + offO[0], v);
+    } else {
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (pS.valid && pLo.valid && vO[r] && take(pS.op + pLo.op + opO[r], rem, only))
+          Mem<io_t>::store1(Yt + pS.off + pLo.off + offO[r], v[r]);
     }
   }
 
   __device__ __forceinline__ void store(io_t* Yt, int64_t rem, const acc_t (&t)[16], int only = -1) const {
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      AxisPart<N, E> pS(i, N * N, Q * Q);  // slab on the slow axis
-      if constexpr (N == 16 && kStoreVec) {
-        Mem<io_t>::store4(Yt + pS.off + pLo.off + offO[0], t[i]);
-      } else if constexpr (kStoreVec) {
-        if (pS.valid && pLo.valid && vO[0] && take(pS.op + pLo.op + opO[0], rem, only))
-          Mem<io_t>::store4(Yt + pS.off + pLo.off + offO[0], t[i]);
-      } else {
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-          if (pS.valid && pLo.valid && vO[r] && take(pS.op + pLo.op + opO[r], rem, only))
-            Mem<io_t>::store1(Yt + pS.off + pLo.off + offO[r], t[i][r]);
-      }
-    }
+    for (int i = 0; i < 16; ++i) store_slab(Yt, rem, i, t[i], only);
   }
 
   // Same isolation rule as the 2-D tile: a packed tile whose result holds a
@@ -372,9 +384,14 @@ __global__ __launch_bounds__(kBlock) void kron2d_kernel(const typename M::io_t* 
   }
 }
 
-// kPipe: the loads of a wavefront's next tile are issued before the current
-// tile is computed, so every wavefront keeps a tile of HBM reads in flight.
-template <class M, int N, bool kVec, bool kTrans, bool kPipe, bool kContig>
+// Loop structure of the 3-D kernel (the variant chosen per (mode, n)):
+//   kPipe    the loads of a wavefront's next tile are issued before the
+//            current tile is computed;
+//   kWindow  > 0: slab loads are kept to a window of kWindow slabs in flight
+//            and stages 1-2 run on each slab as it lands (scheduling barriers
+//            keep the compiler from hoisting every load to the top).  Fewer
+//            bytes in flight per wavefront keep HBM queues short.
+template <class M, int N, bool kVec, bool kTrans, bool kPipe, bool kContig, int kWindow>
 __global__ __launch_bounds__(kBlock) void kron3d_kernel(const typename M::io_t* __restrict__ A,
                                                         const typename M::io_t* __restrict__ B,
                                                         const typename M::io_t* __restrict__ C,
@@ -388,7 +405,46 @@ __global__ __launch_bounds__(kBlock) void kron3d_kernel(const typename M::io_t* 
   const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * kBlock) >> 6;
   const T tile(A, B, C, L, g);
-  if constexpr (kPipe) {
+  if constexpr (kWindow > 0) {
+    // pre: the first kWindow slabs of the wavefront's next tile.  With kPipe
+    // they are requested before the current tile's third stage, otherwise
+    // after its stores.
+    acc_t pre[kWindow];
+    int64_t t = wave;
+    if (t < ntiles) {
+#pragma unroll
+      for (int b = 0; b < kWindow; ++b) tile.load_slab(X + t * kStep, batch - t * T::kOps, b, pre[b]);
+    }
+    for (; t < ntiles; t += nwaves) {
+      const typename M::io_t* Xt = X + t * kStep;
+      const int64_t rem = batch - t * T::kOps;
+      const int64_t tn = t + nwaves;
+      acc_t v[16];
+#pragma unroll
+      for (int b = 0; b < kWindow; ++b) v[b] = pre[b];
+#pragma unroll
+      for (int b = 0; b < 16; ++b) {
+        __builtin_amdgcn_sched_barrier(0);
+        tile.stage12(v[b]);
+        if (b + kWindow < 16) tile.load_slab(Xt, rem, b + kWindow, v[b + kWindow]);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      if constexpr (kPipe) {
+        if (tn < ntiles) {
+#pragma unroll
+          for (int b = 0; b < kWindow; ++b) tile.load_slab(X + tn * kStep, batch - tn * T::kOps, b, pre[b]);
+        }
+      }
+      tile.stage3(v);
+      tile.finish(Xt, Y + t * kStep, rem, v);
+      if constexpr (!kPipe) {
+        if (tn < ntiles) {
+#pragma unroll
+          for (int b = 0; b < kWindow; ++b) tile.load_slab(X + tn * kStep, batch - tn * T::kOps, b, pre[b]);
+        }
+      }
+    }
+  } else if constexpr (kPipe) {
     int64_t t = wave;
     if (t >= ntiles) return;
     acc_t cur[16];

@@ -83,11 +83,11 @@ int launch2d_n(const typename M::io_t* A, const typename M::io_t* B, const typen
   return 0;
 }
 
-template <class M, int N, bool kTrans, bool kVec, bool kPipe, bool kContig>
+template <class M, int N, bool kTrans, bool kVec, bool kPipe, bool kContig, int kWindow>
 void launch3d_k(const typename M::io_t* A, const typename M::io_t* B, const typename M::io_t* C,
                 const typename M::io_t* X, typename M::io_t* Y, int64_t batch, int64_t ntiles, int per_cu,
                 hipStream_t stream) {
-  auto k = kron3d_kernel<M, N, kVec, kTrans, kPipe, kContig>;
+  auto k = kron3d_kernel<M, N, kVec, kTrans, kPipe, kContig, kWindow>;
   hipLaunchKernelGGL(k, dim3(grid_blocks(ntiles, occupancy_blocks(k), per_cu)), dim3(kBlock), 0, stream, A, B, C, X,
                      Y, batch, ntiles);
 }
@@ -98,21 +98,35 @@ void launch3d_v(int variant, const typename M::io_t* A, const typename M::io_t* 
                 hipStream_t stream) {
   switch (variant) {
     case 1:
-      launch3d_k<M, N, kTrans, kVec, true, false>(A, B, C, X, Y, batch, ntiles, per_cu, stream);
+      launch3d_k<M, N, kTrans, kVec, true, false, 0>(A, B, C, X, Y, batch, ntiles, per_cu, stream);
       break;
     case 2:
-      launch3d_k<M, N, kTrans, kVec, false, true>(A, B, C, X, Y, batch, ntiles, per_cu, stream);
+      launch3d_k<M, N, kTrans, kVec, false, true, 0>(A, B, C, X, Y, batch, ntiles, per_cu, stream);
       break;
     case 3:
-      launch3d_k<M, N, kTrans, kVec, true, true>(A, B, C, X, Y, batch, ntiles, per_cu, stream);
+      launch3d_k<M, N, kTrans, kVec, true, true, 0>(A, B, C, X, Y, batch, ntiles, per_cu, stream);
+      break;
+    case 4:
+      launch3d_k<M, N, kTrans, kVec, false, true, 2>(A, B, C, X, Y, batch, ntiles, per_cu, stream);
+      break;
+    case 5:
+      launch3d_k<M, N, kTrans, kVec, false, true, 4>(A, B, C, X, Y, batch, ntiles, per_cu, stream);
+      break;
+    case 6:
+      launch3d_k<M, N, kTrans, kVec, true, true, 2>(A, B, C, X, Y, batch, ntiles, per_cu, stream);
+      break;
+    case 7:
+      launch3d_k<M, N, kTrans, kVec, true, true, 4>(A, B, C, X, Y, batch, ntiles, per_cu, stream);
       break;
     default:
-      launch3d_k<M, N, kTrans, kVec, false, false>(A, B, C, X, Y, batch, ntiles, per_cu, stream);
+      launch3d_k<M, N, kTrans, kVec, false, false, 0>(A, B, C, X, Y, batch, ntiles, per_cu, stream);
   }
 }
 
-// 3-D variants: bit 0 = next tile prefetched, bit 1 = contiguous loads
-// (operand slabs along the slow axis, a second lane-group exchange).
+// 3-D variants: 0 plain, 1 next tile prefetched, 2 contiguous 1 KiB rows
+// (operand slabs along the slow axis, a second lane-group exchange),
+// 3 = 1 + 2, 4/5 contiguous rows with a window of 2/4 slab loads in flight,
+// 6/7 = 4/5 with the next tile's first slabs requested before stage 3.
 template <class M, int N, bool kTrans>
 int launch3d_n(const typename M::io_t* A, const typename M::io_t* B, const typename M::io_t* C,
                const typename M::io_t* X, typename M::io_t* Y, int64_t batch, hipStream_t stream, int mode) {
@@ -147,17 +161,15 @@ int launch2d(int n, const typename M::io_t* A, const typename M::io_t* B, const 
   }
 }
 
-template <class M, bool kTrans>
-int launch3d(int n, const typename M::io_t* A, const typename M::io_t* B, const typename M::io_t* C,
-             const typename M::io_t* X, typename M::io_t* Y, int64_t batch, hipStream_t stream, int mode) {
-  switch (n) {
-#define KRON_CASE(NN) \
-  case NN:            \
-    return launch3d_n<M, NN, kTrans>(A, B, C, X, Y, batch, stream, mode);
-    KRON_N_CASES(KRON_CASE)
-#undef KRON_CASE
-    default:
-      return -1;
+// n in [NLO, NHI] (one translation unit per range keeps builds parallel)
+template <class M, bool kTrans, int NN, int NHI>
+int launch3d_range(int n, const typename M::io_t* A, const typename M::io_t* B, const typename M::io_t* C,
+                   const typename M::io_t* X, typename M::io_t* Y, int64_t batch, hipStream_t stream, int mode) {
+  if constexpr (NN > NHI) {
+    return -1;
+  } else {
+    if (n == NN) return launch3d_n<M, NN, kTrans>(A, B, C, X, Y, batch, stream, mode);
+    return launch3d_range<M, kTrans, NN + 1, NHI>(n, A, B, C, X, Y, batch, stream, mode);
   }
 }
 

@@ -39,4 +39,34 @@ int fwd2d_bf16(int n, const uint16_t* A, const uint16_t* B, const uint16_t* X, u
 int fwd3d_bf16(int n, const uint16_t* A, const uint16_t* B, const uint16_t* C, const uint16_t* X, uint16_t* Y,
                int64_t batch, hipStream_t s);
 
+// 3-D launches split by n range (kron_<mode>_3d_lo/hi.hip).
+int fwd3d_f32_lo(int n, const float* A, const float* B, const float* C, const float* X, float* Y, int64_t batch,
+                hipStream_t s, bool trans);
+int fwd3d_f32_hi(int n, const float* A, const float* B, const float* C, const float* X, float* Y, int64_t batch,
+                hipStream_t s, bool trans);
+int fwd3d_f64_lo(int n, const double* A, const double* B, const double* C, const double* X, double* Y, int64_t batch,
+                hipStream_t s, bool trans);
+int fwd3d_f64_hi(int n, const double* A, const double* B, const double* C, const double* X, double* Y, int64_t batch,
+                hipStream_t s, bool trans);
+int fwd3d_bf16x3_lo(int n, const float* A, const float* B, const float* C, const float* X, float* Y, int64_t batch,
+                hipStream_t s);
+int fwd3d_bf16x3_hi(int n, const float* A, const float* B, const float* C, const float* X, float* Y, int64_t batch,
+                hipStream_t s);
+int fwd3d_bf16_lo(int n, const uint16_t* A, const uint16_t* B, const uint16_t* C, const uint16_t* X, uint16_t* Y, int64_t batch,
+                hipStream_t s);
+int fwd3d_bf16_hi(int n, const uint16_t* A, const uint16_t* B, const uint16_t* C, const uint16_t* X, uint16_t* Y, int64_t batch,
+                hipStream_t s);
+
+// Factor gradients (kron_grad.hip).  ws holds grad_workspace_bytes().
+int64_t grad_waves(int dim, int n, int64_t batch);
+size_t grad_workspace_bytes(int dim, int n, int64_t batch, int elem_bytes);
+int grad2d_f32(int n, const float* A, const float* B, const float* X, const float* dY, float* dA, float* dB,
+               int64_t batch, void* ws, hipStream_t s);
+int grad3d_f32(int n, const float* A, const float* B, const float* C, const float* X, const float* dY, float* dA,
+               float* dB, float* dC, int64_t batch, void* ws, hipStream_t s);
+int grad2d_f64(int n, const double* A, const double* B, const double* X, const double* dY, double* dA, double* dB,
+               int64_t batch, void* ws, hipStream_t s);
+int grad3d_f64(int n, const double* A, const double* B, const double* C, const double* X, const double* dY,
+               double* dA, double* dB, double* dC, int64_t batch, void* ws, hipStream_t s);
+
 }  // namespace kron

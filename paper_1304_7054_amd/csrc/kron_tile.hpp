@@ -129,6 +129,7 @@ __device__ __forceinline__ T tile_entry(const T* M, int row, int col) {
 struct ModeF32 {
   using io_t = float;
   using acc_t = f32x4;
+  using elem_t = float;
   using fac_t = f32x4;
   static constexpr int kBytes = 4;
   __device__ static constexpr int drow(int g, int r) { return 4 * g + r; }
@@ -158,6 +159,7 @@ struct ModeF32 {
 struct ModeF64 {
   using io_t = double;
   using acc_t = f64x4;
+  using elem_t = double;
   using fac_t = f64x4;
   static constexpr int kBytes = 8;
   __device__ static constexpr int drow(int g, int r) { return g + 4 * r; }

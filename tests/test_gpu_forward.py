@@ -227,8 +227,8 @@ def test_launch_variants_agree(mode, dim, n):
     want = _oracle(dim, n, gu.rounded_inputs(mode, mats), gu.rounded_inputs(mode, [X])[0], batch)
     refs = {}
     try:
-        for variant in ([0, 1, 2, 3] if dim == 3 else [0, 1, 2]):
-            order = (variant >> 1) if dim == 3 else 0
+        for variant in ([0, 1, 2, 3, 4, 5, 6, 7] if dim == 3 else [0, 1, 2]):
+            order = (1 if variant >= 2 else 0) if dim == 3 else 0
             for blocks in (0, 1):
                 kron.kron_set_launch(mcode, dim, n, blocks, variant)
                 got = gu.run(mode, dim, n, mats, X, batch)
