@@ -38,6 +38,9 @@ def parse():
     p.add_argument("--warmup", type=int, default=5)
     p.add_argument("--only-headline", action="store_true", help="skip the other modes")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    p.add_argument("--summarize-profiles", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
+                   help="read rocprofv3 outputs of this script (kernel trace, FETCH_SIZE, WRITE_SIZE runs "
+                        "with --copy-calibration) and write the summary and traffic record under profiles/")
     p.add_argument("--copy-calibration", action="store_true",
                    help="first run three plain 1 GiB device copies (a kernel of known traffic for "
                         "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -140,6 +143,76 @@ def measure(torch, mode, dim, n, batch, steps, warmup, seed):
     return out
 
 
+def measure_grouped(torch, steps, warmup):
+    """The 500,000-operand mixed workload (n in 2..16, 70/30 2-D/3-D, one
+    group per (dim, n)) in one persistent launch, replayed from a HIP graph."""
+    import paper_1304_7054_amd as kron
+    import workloads
+    probs = workloads.workload4()
+    groups, flops, alg = [], 0, 0
+    for p in probs:
+        g = {"dim": p.dim, "n": p.n, "count": p.batch, "X": torch.from_numpy(p.X).to("cuda"),
+             "Y": torch.empty(p.X.size, device="cuda")}
+        for k, m in zip("ABC", (p.A, p.B, p.C)):
+            if m is not None:
+                g[k] = torch.from_numpy(m).to("cuda")
+        groups.append(g)
+        flops += p.flops()
+        alg += 2 * 4 * p.X.size
+    ws = torch.empty(kron.kron_grouped_workspace_size(groups), dtype=torch.uint8, device="cuda")
+    kron.kron_grouped_prepare(groups, ws)
+    exe = kron.kron_graph_capture_grouped(ws)
+    try:
+        wall, kmean, kmin = time_launches(torch, lambda stream=None: kron.kron_graph_launch(exe, stream), (),
+                                          steps, warmup)
+        ewall, emean, emin = time_launches(torch, lambda stream=None: kron.kron_grouped_launch(ws, stream), (),
+                                           steps, warmup)
+    finally:
+        kron.kron_graph_destroy(exe)
+    torch.cuda.synchronize()
+    # sampled parity of the graph replay
+    import oracle
+    rng = np.random.default_rng(7)
+    worst = 0.0
+    for p, g in zip(probs, groups):
+        e = p.n ** p.dim
+        Y = g["Y"]
+        mats = [m.astype(np.float64) for m in (p.A, p.B, p.C) if m is not None]
+        for q in rng.integers(0, p.batch, 4):
+            want = (oracle.kron2d if p.dim == 2 else oracle.kron3d)(p.n, *mats, p.X[q * e:(q + 1) * e], 1, "f64")
+            got = Y[q * e:(q + 1) * e].double().cpu().numpy()
+            worst = max(worst, float(np.linalg.norm(got - want) / np.linalg.norm(want)))
+    del groups, ws
+    torch.cuda.empty_cache()
+    return {"mode": "f32 grouped (graph replay)", "operands": workloads.MIXED_COUNT, "groups": len(probs),
+            "ms": round(kmean, 4), "ms_min": round(kmin, 4), "eager_ms": round(emean, 4),
+            "gflops": round(flops / (kmean * 1e-3) / 1e9, 1), "gbs": round(alg / (kmean * 1e-3) / 1e9, 1),
+            "hbm_frac": round(alg / (kmean * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "alg_bytes": alg,
+            "sampled_max_rel_err": worst}
+
+
+def measure_backward(torch, steps, warmup):
+    """dX + dA + dB + dC of the 3-D n=16 FP32 workload (reads X and dY,
+    writes dX: three 1 GiB streams)."""
+    import paper_1304_7054_amd as kron
+    import workloads
+    n, batch = 16, workloads.BATCH_3D[16]
+    mats, X, _ = make_inputs(torch, 3, n, batch, "f32", 2)
+    dY = torch.randn_like(X)
+    dX = torch.empty_like(X)
+    grads = [torch.empty(n * n, device="cuda") for _ in range(3)]
+    ws = torch.empty(kron.kron_backward_workspace_size(3, n, batch, kron.MODE_F32), dtype=torch.uint8,
+                     device="cuda")
+    fn = lambda stream=None: kron.kron3d_backward_f32(n, *mats, X, dY, dX, *grads, batch, ws, stream)
+    wall, kmean, kmin = time_launches(torch, fn, (), max(5, steps // 5), warmup)
+    alg = 3 * X.numel() * 4
+    del mats, X, dY, dX, grads, ws
+    torch.cuda.empty_cache()
+    return {"mode": "f32 backward 3-D n=16 (dX, dA, dB, dC)", "batch": batch, "ms": round(kmean, 4),
+            "gbs": round(alg / (kmean * 1e-3) / 1e9, 1), "hbm_frac": round(alg / (kmean * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "alg_bytes": alg}
+
+
 def cpu_baseline(n=16, target_s=12.0):
     """The FP32 CPU oracle on a bounded sample of the headline workload."""
     import oracle
@@ -177,8 +250,60 @@ def traffic_record(khash):
     return rec.get("bytes_per_dispatch")
 
 
+HEADLINE_KERNEL = "kron::kron3d_kernel<kron::ModeF32, 16,"
+CALIBRATION_KERNEL = "__amd_rocclr_copyBuffer"
+
+
+def _csv(dirname, suffix):
+    import csv
+    import glob
+    files = glob.glob(os.path.join(dirname, "**", f"*{suffix}"), recursive=True)
+    if not files:
+        raise FileNotFoundError(f"no *{suffix} under {dirname}")
+    with open(files[0]) as f:
+        return list(csv.DictReader(f))
+
+
+def summarize_profiles(trace_dir, fetch_dir, write_dir):
+    """Summary of the rocprofv3 runs of this script: the headline kernel's
+    duration (kernel trace) and its HBM bytes per dispatch from FETCH_SIZE and
+    WRITE_SIZE (KiB per dispatch), each scaled by what the same counter reads
+    for the plain 1 GiB device copy the --copy-calibration option issues
+    (1 GiB read, 1 GiB written)."""
+    stats = _csv(trace_dir, "kernel_stats.csv")
+    head = [r for r in stats if HEADLINE_KERNEL in r["Name"]]
+    if not head:
+        raise RuntimeError("headline kernel not in the trace")
+    h = head[0]
+    out = {"kernel": h["Name"], "calls": int(h["Calls"]), "avg_ns": float(h["AverageNs"]),
+           "min_ns": float(h["MinNs"]), "max_ns": float(h["MaxNs"])}
+    one_gib_kib = float(1 << 20)
+    for tag, d, counter in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
+        rows = [r for r in _csv(d, "counter_collection.csv") if r["Counter_Name"] == counter]
+        kern = [float(r["Counter_Value"]) for r in rows if HEADLINE_KERNEL in r["Kernel_Name"]]
+        cal = [float(r["Counter_Value"]) for r in rows if r["Kernel_Name"] == CALIBRATION_KERNEL]
+        # the calibration copies are the copyBuffer dispatches of 1 GiB: the largest ones
+        cal = sorted(cal)[-3:]
+        scale = one_gib_kib / (sum(cal) / len(cal))
+        out[f"{tag}_kib_raw"] = sum(kern) / len(kern)
+        out[f"{tag}_calibration_kib_raw"] = sum(cal) / len(cal)
+        out[f"{tag}_scale"] = scale
+        out[f"{tag}_bytes"] = out[f"{tag}_kib_raw"] * scale * 1024
+    out["bytes_per_dispatch"] = out["fetch_bytes"] + out["write_bytes"]
+    out["alg_bytes_per_dispatch"] = 2 * 65536 * 16 ** 3 * 4
+    out["kernel_hash"] = kernel_hash()
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    with open(os.path.join(ROOT, "profiles", "kron3d_f32_n16_traffic.json"), "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out, indent=1))
+    return out
+
+
 def main():
     args = parse()
+    if args.summarize_profiles:
+        summarize_profiles(*args.summarize_profiles)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the batch splits into independent per-GPU shards; see DESIGN.md)", file=sys.stderr)
@@ -213,6 +338,10 @@ def main():
         for mode, dim, n, batch, seed in plan:
             others.append(measure(torch, mode, dim, n, batch, max(10, args.steps // 2), args.warmup, seed))
             print(f"# measured {mode} {dim}-D n={n}: {others[-1]['gflops']} GFLOP/s", file=sys.stderr, flush=True)
+        others.append(measure_grouped(torch, max(10, args.steps // 2), args.warmup))
+        print(f"# measured grouped mixed: {others[-1]['gflops']} GFLOP/s", file=sys.stderr, flush=True)
+        others.append(measure_backward(torch, args.steps, args.warmup))
+        print(f"# measured backward: {others[-1]['ms']} ms", file=sys.stderr, flush=True)
 
     khash = kernel_hash()
     roof = {"bound": "hbm", "achieved": head["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -228,6 +357,7 @@ def main():
                    "dim": 3, "n": 16, "batch": head["batch"]},
         "roofline": roof,
         "headline": head,
+        "bf16x3": next((o for o in others if o.get("mode") == "bf16x3" and o.get("dim") == 3), None),
         "modes": others,
         "kernel_hash": khash,
     }

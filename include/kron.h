@@ -112,6 +112,48 @@ int kron2d_batched_adjoint_f64(int n, const double* A, const double* B, const do
 int kron3d_batched_adjoint_f64(int n, const double* A, const double* B, const double* C,
                                const double* X, double* Y, int64_t batch, hipStream_t stream);
 
+/* ---- mixed batches: one launch over many groups ----------------------------- */
+
+/* One group of operands sharing the factors A, B (and C for dim 3), stored as
+   for kron2d/kron3d_batched; `mode` is KRON_MODE_F32 or KRON_MODE_BF16X3
+   (FP32 arrays).  C may be NULL for dim 2. */
+typedef struct kron_group {
+  int32_t dim;      /* 2 or 3 */
+  int32_t n;        /* 1..16 */
+  int32_t mode;     /* KRON_MODE_F32 or KRON_MODE_BF16X3 */
+  int32_t reserved; /* set to 0 */
+  const void* A;
+  const void* B;
+  const void* C;
+  const void* X;
+  void* Y;
+  int64_t count; /* operands in the group, >= 0 */
+} kron_group_t;
+
+/* The batched action of Section 2.2 over a batch that mixes sizes and 2-D /
+   3-D operands, in ONE persistent kernel launch (so one graph node).
+   kron_grouped_prepare builds the work plan on the host (groups cut into
+   runs of tiles of about equal cost, runs handed to wavefronts largest
+   first) and copies it into `ws`, caller-owned device memory of at least
+   kron_grouped_workspace_size() bytes; it synchronises `stream`.  The plan
+   keeps the group pointers: the arrays must stay valid while it is used.
+   kron_grouped_launch(ws) then runs every group; it is asynchronous, takes
+   no host-side work besides the launch, and can be captured in a HIP graph.
+   The plan is bound to this process and to the device it was prepared on;
+   preparing the same `ws` again replaces it.  Returns 0 or -k (argument k
+   invalid: -1 also for any bad group descriptor; -4 workspace too small). */
+size_t kron_grouped_workspace_size(const kron_group_t* groups, int ngroups);
+int kron_grouped_prepare(const kron_group_t* groups, int ngroups, void* ws, size_t ws_bytes,
+                         hipStream_t stream);
+int kron_grouped_launch(const void* ws, hipStream_t stream);
+
+/* HIP graphs for launch-bound callers: capture one kron_grouped_launch(ws)
+   into an instantiated graph (`*graph_exec`), replay it on any stream, and
+   release it.  Capture happens on a private stream of default priority. */
+int kron_graph_capture_grouped(const void* ws, void** graph_exec);
+int kron_graph_launch(void* graph_exec, hipStream_t stream);
+int kron_graph_destroy(void* graph_exec);
+
 /* ---- backward ---------------------------------------------------------------- */
 
 /* Gradients of L = sum_p <dY_p, Y_p> for the forward actions above (the

@@ -29,6 +29,13 @@ from ._binding import (  # noqa: F401
     kron3d_batched_f32,
     kron3d_batched_f32_bf16x3,
     kron3d_batched_f64,
+    kron_graph_capture_grouped,
+    kron_graph_destroy,
+    kron_graph_launch,
+    kron_grouped_launch,
+    kron_grouped_prepare,
+    kron_grouped_workspace_size,
+    KronGroup,
     kron_get_launch,
     kron_set_launch,
     lib,

@@ -28,6 +28,14 @@ class KronError(RuntimeError):
 
 _LIB = None
 
+
+class KronGroup(ctypes.Structure):
+    """kron_group_t of include/kron.h."""
+    _fields_ = [("dim", ctypes.c_int32), ("n", ctypes.c_int32), ("mode", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("A", ctypes.c_void_p), ("B", ctypes.c_void_p),
+                ("C", ctypes.c_void_p), ("X", ctypes.c_void_p), ("Y", ctypes.c_void_p),
+                ("count", ctypes.c_int64)]
+
 # (name, argument kinds); 'i' int, 'l' int64, 'p' pointer, 'S' stream, 'z' size_t
 SIGNATURES = {
     "kron2d_batched_f32": "ipppplS",
@@ -70,6 +78,19 @@ def lib():
         L.kron_version.restype = ctypes.c_char_p
         L.kron_backward_workspace_size.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int]
         L.kron_backward_workspace_size.restype = ctypes.c_size_t
+        L.kron_grouped_workspace_size.argtypes = [ctypes.POINTER(KronGroup), ctypes.c_int]
+        L.kron_grouped_workspace_size.restype = ctypes.c_size_t
+        L.kron_grouped_prepare.argtypes = [ctypes.POINTER(KronGroup), ctypes.c_int, ctypes.c_void_p,
+                                           ctypes.c_size_t, ctypes.c_void_p]
+        L.kron_grouped_prepare.restype = ctypes.c_int
+        L.kron_grouped_launch.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+        L.kron_grouped_launch.restype = ctypes.c_int
+        L.kron_graph_capture_grouped.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]
+        L.kron_graph_capture_grouped.restype = ctypes.c_int
+        L.kron_graph_launch.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+        L.kron_graph_launch.restype = ctypes.c_int
+        L.kron_graph_destroy.argtypes = [ctypes.c_void_p]
+        L.kron_graph_destroy.restype = ctypes.c_int
         L.kron_set_launch.argtypes = [ctypes.c_int] * 5
         L.kron_set_launch.restype = ctypes.c_int
         L.kron_get_launch.argtypes = [ctypes.c_int] * 3 + [ctypes.POINTER(ctypes.c_int)] * 2
@@ -243,3 +264,57 @@ def kron2d_backward_f64(n, A, B, X, dY, dX, dA, dB, batch, ws=None, stream=None)
 def kron3d_backward_f64(n, A, B, C, X, dY, dX, dA, dB, dC, batch, ws=None, stream=None):
     return _backward_call("kron3d_backward_f64", 3, torch.float64, MODE_F64, n, (A, B, C), X, dY, dX,
                           (dA, dB, dC), batch, ws, stream)
+
+
+def _groups_array(groups):
+    """groups: iterable of dicts with dim, n, A, B, (C), X, Y, count and optional
+    mode (MODE_F32 default or MODE_BF16X3); tensors are FP32 on the GPU."""
+    groups = list(groups)
+    arr = (KronGroup * max(1, len(groups)))()
+    for i, g in enumerate(groups):
+        dim, n, count = int(g["dim"]), int(g["n"]), int(g["count"])
+        mode = int(g.get("mode", MODE_F32))
+        if dim not in (2, 3) or not 1 <= n <= 16 or count < 0:
+            raise ValueError(f"group {i}: bad dim/n/count")
+        if mode not in (MODE_F32, MODE_BF16X3):
+            raise ValueError(f"group {i}: mode must be MODE_F32 or MODE_BF16X3")
+        size = count * n ** dim
+        mats = [_arr(g[k], torch.float32, n * n, f"group {i} {k}") for k in ("A", "B", "C")[:dim]]
+        px = _arr(g["X"], torch.float32, size, f"group {i} X")
+        py = _arr(g["Y"], torch.float32, size, f"group {i} Y")
+        if size > 0 and g["X"].data_ptr() == g["Y"].data_ptr():
+            raise ValueError(f"group {i}: X and Y must not overlap")
+        arr[i] = KronGroup(dim, n, mode, 0, mats[0], mats[1], mats[2] if dim == 3 else None, px, py, count)
+    return arr, len(groups)
+
+
+def kron_grouped_workspace_size(groups):
+    arr, k = _groups_array(groups)
+    return int(lib().kron_grouped_workspace_size(arr, k))
+
+
+def kron_grouped_prepare(groups, ws, stream=None):
+    """Build the work plan of `groups` into device workspace `ws` (uint8 tensor);
+    the group tensors must outlive every launch of the plan."""
+    arr, k = _groups_array(groups)
+    return _call("kron_grouped_prepare", arr, k, ctypes.c_void_p(ws.data_ptr()),
+                 ws.numel() * ws.element_size(), _stream(stream))
+
+
+def kron_grouped_launch(ws, stream=None):
+    return _call("kron_grouped_launch", ctypes.c_void_p(ws.data_ptr()), _stream(stream))
+
+
+def kron_graph_capture_grouped(ws):
+    """Instantiated HIP graph (an opaque handle) holding one grouped launch."""
+    h = ctypes.c_void_p(0)
+    _call("kron_graph_capture_grouped", ctypes.c_void_p(ws.data_ptr()), ctypes.byref(h))
+    return h.value
+
+
+def kron_graph_launch(graph_exec, stream=None):
+    return _call("kron_graph_launch", ctypes.c_void_p(graph_exec), _stream(stream))
+
+
+def kron_graph_destroy(graph_exec):
+    return _call("kron_graph_destroy", ctypes.c_void_p(graph_exec))

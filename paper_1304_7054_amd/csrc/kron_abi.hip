@@ -49,8 +49,8 @@ LaunchShape default_shape(int mode, int dim, int n) {
   if (dim == 3) {
     switch (mode) {
       case 0: return LaunchShape{0, 4};  // FP32: contiguous rows, 2-slab window
-      case 1: return LaunchShape{0, 3};  // FP64: contiguous rows, next tile prefetched
-      case 2: return LaunchShape{2, 5};  // bf16x3: 4-slab window, 2 workgroups per CU
+      case 1: return LaunchShape{2, 7};  // FP64: 4-slab window + next tile, 2 workgroups per CU
+      case 2: return LaunchShape{2, 6};  // bf16x3: 2-slab window + next tile, 2 workgroups per CU
       default: return LaunchShape{0, 5}; // bf16 storage: 4-slab window
     }
   }
@@ -298,6 +298,61 @@ int kron3d_backward_f64(int n, const double* A, const double* B, const double* C
   }
   if (dA || dB || dC) return finish_launch(kron::grad3d_f64(n, A, B, C, X, dY, dA, dB, dC, batch, ws, stream));
   return 0;
+}
+
+size_t kron_grouped_workspace_size(const kron_group_t* groups, int ngroups) {
+  return kron::grouped_workspace_bytes(groups, ngroups);
+}
+
+int kron_grouped_prepare(const kron_group_t* groups, int ngroups, void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (!groups) return -1;
+  if (ngroups <= 0) return -2;
+  return kron::grouped_prepare(groups, ngroups, ws, ws_bytes, stream);
+}
+
+int kron_grouped_launch(const void* ws, hipStream_t stream) {
+  if (!ws) return -1;
+  return finish_launch(kron::grouped_launch(ws, stream));
+}
+
+int kron_graph_capture_grouped(const void* ws, void** graph_exec) {
+  if (!ws) return -1;
+  if (!graph_exec) return -2;
+  *graph_exec = nullptr;
+  hipStream_t s = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+  if (e != hipSuccess) return (int)e;
+  hipGraph_t graph = nullptr;
+  int rc = 0;
+  e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    rc = kron::grouped_launch(ws, s);
+    hipError_t e2 = hipStreamEndCapture(s, &graph);
+    if (rc == 0 && e2 != hipSuccess) rc = (int)e2;
+  } else {
+    rc = (int)e;
+  }
+  if (rc == 0) {
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) rc = (int)e;
+    else *graph_exec = exec;
+  }
+  if (graph) (void)hipGraphDestroy(graph);
+  (void)hipStreamDestroy(s);
+  return rc;
+}
+
+int kron_graph_launch(void* graph_exec, hipStream_t stream) {
+  if (!graph_exec) return -1;
+  hipError_t e = hipGraphLaunch(static_cast<hipGraphExec_t>(graph_exec), stream);
+  return e == hipSuccess ? 0 : (int)e;
+}
+
+int kron_graph_destroy(void* graph_exec) {
+  if (!graph_exec) return -1;
+  hipError_t e = hipGraphExecDestroy(static_cast<hipGraphExec_t>(graph_exec));
+  return e == hipSuccess ? 0 : (int)e;
 }
 
 const char* kron_status_string(int status) {

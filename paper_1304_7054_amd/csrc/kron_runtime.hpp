@@ -6,6 +6,8 @@
 
 #include <cstdint>
 
+struct kron_group;
+
 namespace kron {
 
 // Compute units of the current device (cached per device ordinal).
@@ -56,6 +58,11 @@ int fwd3d_bf16_lo(int n, const uint16_t* A, const uint16_t* B, const uint16_t* C
                 hipStream_t s);
 int fwd3d_bf16_hi(int n, const uint16_t* A, const uint16_t* B, const uint16_t* C, const uint16_t* X, uint16_t* Y, int64_t batch,
                 hipStream_t s);
+
+// Grouped launch (kron_grouped.hip).
+size_t grouped_workspace_bytes(const struct kron_group* g, int ngroups);
+int grouped_prepare(const struct kron_group* g, int ngroups, void* ws, size_t ws_bytes, hipStream_t stream);
+int grouped_launch(const void* ws, hipStream_t stream);
 
 // Factor gradients (kron_grad.hip).  ws holds grad_workspace_bytes().
 int64_t grad_waves(int dim, int n, int64_t batch);
