@@ -63,8 +63,10 @@ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 // ---- device side ----------------------------------------------------------------
 
+// The item routines stay out of line: inlining all (mode, dim, n) paths into
+// the one kernel made the register allocator spill heavily.
 template <class M, int N, bool kVec>
-__device__ __forceinline__ void run_item_2d(const GroupDesc& gd, const Item& it, int L, int g) {
+__device__ __attribute__((noinline)) void run_item_2d(const GroupDesc& gd, const Item& it, int L, int g) {
   using T = Tile2D<M, N, kVec, false>;
   using io_t = typename M::io_t;
   using acc_t = typename M::acc_t;
@@ -92,7 +94,7 @@ __device__ __forceinline__ void run_item_2d(const GroupDesc& gd, const Item& it,
 }
 
 template <class M, int N, bool kVec>
-__device__ __forceinline__ void run_item_3d(const GroupDesc& gd, const Item& it, int L, int g) {
+__device__ __attribute__((noinline)) void run_item_3d(const GroupDesc& gd, const Item& it, int L, int g) {
   using T = Tile3D<M, N, kVec, false, true>;
   using io_t = typename M::io_t;
   using acc_t = typename M::acc_t;
