@@ -191,17 +191,32 @@ int kron3d_backward_f64(int n, const double* A, const double* B, const double* C
 
 /* How the kernels for (mode, dim, n) are launched: `blocks_per_cu` 256-thread
    workgroups per compute unit (0 = as many as can be resident; -1 = back to
-   the built-in default) and a kernel `variant` (2-D: tiles in flight per
-   wavefront, 0 -> 4, 1 -> 8, 2 -> 2; 3-D: bit 0 = the next tile's loads are
-   issued before the current tile is computed, bit 1 = operands are read and
-   written in fully contiguous 1 KiB rows at the cost of a second
-   register exchange).  The paper
+   the built-in default) and a kernel `variant`:
+     2-D: 0/1/2 = 4/8/2 tiles in flight per wavefront, direct loads;
+          3 = tiles staged through LDS (n != 16).
+     3-D: 0 plain; 1 next tile prefetched; 2 contiguous 1 KiB rows (a second
+          register exchange); 3 = 1 + 2; 4/5 = contiguous rows with a window
+          of 2/4 slab loads in flight; 6/7 = 4/5 with the next tile's first
+          slabs requested early; 8 = tiles staged through LDS (n != 16, FP32,
+          bf16x3 and bf16 storage).  A variant a size cannot use falls back
+          to 0.  The paper
    picks its kernel method by matrix size and fixes the number of thread
    blocks (Sections 4 and 5); here the choice is a per-(mode, dim, n) table
    that an autotuner can fill.  Process-wide, not thread-safe against
    concurrent launches of the same (mode, dim, n).  Returns 0 or -k. */
 int kron_set_launch(int mode, int dim, int n, int blocks_per_cu, int variant);
 int kron_get_launch(int mode, int dim, int n, int* blocks_per_cu, int* variant);
+
+/* Autotuner: time every launch shape (variants x 0..4 workgroups per CU) of
+   (mode, dim, n) on the caller's device buffers (A, B, C, X read; Y is
+   overwritten; C may be NULL for dim 2; element type as for the mode's
+   entry points), `reps` timed launches each on `stream` with HIP events,
+   keep the fastest in the launch-shape table and report it (any out
+   pointer may be NULL).  Synchronises `stream`.  On error the entry is
+   reset to the built-in default. */
+int kron_autotune(int mode, int dim, int n, const void* A, const void* B, const void* C,
+                  const void* X, void* Y, int64_t batch, int reps, hipStream_t stream,
+                  int* best_blocks, int* best_variant, float* best_ms);
 
 /* ---- status -------------------------------------------------------------- */
 

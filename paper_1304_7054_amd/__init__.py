@@ -36,9 +36,25 @@ from ._binding import (  # noqa: F401
     kron_grouped_prepare,
     kron_grouped_workspace_size,
     KronGroup,
+    kron_autotune,
     kron_get_launch,
     kron_set_launch,
     lib,
     status_string,
     version,
 )
+
+
+def _load_tuning():
+    import os
+    path = os.environ.get("KRON_TUNE_CACHE")
+    if path and os.path.exists(path):
+        from . import tune
+        tune.load(path)
+
+
+try:
+    _load_tuning()
+except Exception as exc:  # a stale or foreign table must not break import
+    import warnings
+    warnings.warn(f"KRON_TUNE_CACHE not applied: {exc}")

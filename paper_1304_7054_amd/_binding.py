@@ -91,6 +91,10 @@ def lib():
         L.kron_graph_launch.restype = ctypes.c_int
         L.kron_graph_destroy.argtypes = [ctypes.c_void_p]
         L.kron_graph_destroy.restype = ctypes.c_int
+        L.kron_autotune.argtypes = [ctypes.c_int] * 3 + [ctypes.c_void_p] * 5 + [
+            ctypes.c_int64, ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int),
+            ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_float)]
+        L.kron_autotune.restype = ctypes.c_int
         L.kron_set_launch.argtypes = [ctypes.c_int] * 5
         L.kron_set_launch.restype = ctypes.c_int
         L.kron_get_launch.argtypes = [ctypes.c_int] * 3 + [ctypes.POINTER(ctypes.c_int)] * 2
@@ -318,3 +322,23 @@ def kron_graph_launch(graph_exec, stream=None):
 
 def kron_graph_destroy(graph_exec):
     return _call("kron_graph_destroy", ctypes.c_void_p(graph_exec))
+
+
+_MODE_DTYPE = {MODE_F32: torch.float32, MODE_F64: torch.float64, MODE_BF16X3: torch.float32,
+               MODE_BF16: torch.bfloat16}
+
+
+def kron_autotune(mode, dim, n, A, B, C, X, Y, batch, reps=10, stream=None):
+    """Time every launch shape of (mode, dim, n) on these buffers, keep the
+    fastest; returns (blocks_per_cu, variant, ms)."""
+    dt = _MODE_DTYPE[int(mode)]
+    n, batch = int(n), int(batch)
+    size = batch * n ** dim
+    mats = [_arr(M, dt, n * n, f"factor {i}") for i, M in enumerate((A, B, C)[:dim])]
+    if dim == 2:
+        mats.append(None)
+    px, py = _arr(X, dt, size, "X"), _arr(Y, dt, size, "Y")
+    b, v, ms = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_float(0)
+    _call("kron_autotune", int(mode), int(dim), n, *mats, px, py, batch, int(reps), _stream(stream),
+          ctypes.byref(b), ctypes.byref(v), ctypes.byref(ms))
+    return b.value, v.value, ms.value

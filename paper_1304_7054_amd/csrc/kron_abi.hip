@@ -45,7 +45,11 @@ void init_shapes() {
 // Built-in defaults, measured on MI355X at n = 16 with 1 GiB batches (the
 // autotuner refines them per n).
 LaunchShape default_shape(int mode, int dim, int n) {
-  (void)n;
+  if (n != 16) {
+    // staged through LDS (3-D only for elements of at most 4 bytes)
+    if (dim == 2) return LaunchShape{0, 3};
+    if (mode != 1) return LaunchShape{0, 8};
+  }
   if (dim == 3) {
     switch (mode) {
       case 0: return LaunchShape{0, 4};  // FP32: contiguous rows, 2-slab window
@@ -72,7 +76,7 @@ int set_launch_shape(int mode, int dim, int n, int blocks_per_cu, int variant) {
   if (dim < 2 || dim > 3) return -2;
   if (n < 1 || n > 16) return -3;
   if (blocks_per_cu < -1 || blocks_per_cu > 64) return -4;
-  if (variant < 0 || variant > (dim == 3 ? 7 : 2)) return -5;
+  if (variant < 0 || variant > (dim == 3 ? 8 : 3)) return -5;
   g_shape[mode][dim - 2][n].store(blocks_per_cu < 0 ? -1 : blocks_per_cu * 16 + variant, std::memory_order_relaxed);
   return 0;
 }
@@ -373,6 +377,72 @@ const char* kron_version(void) { return "kron 0.1 gfx950"; }
 
 int kron_set_launch(int mode, int dim, int n, int blocks_per_cu, int variant) {
   return kron::set_launch_shape(mode, dim, n, blocks_per_cu, variant);
+}
+
+int kron_autotune(int mode, int dim, int n, const void* A, const void* B, const void* C, const void* X, void* Y,
+                  int64_t batch, int reps, hipStream_t stream, int* best_blocks, int* best_variant,
+                  float* best_ms) {
+  if (mode < 0 || mode > 3) return -1;
+  if (dim < 2 || dim > 3) return -2;
+  if (n < 1 || n > KRON_MAX_N) return -3;
+  if (!A) return -4;
+  if (!B) return -5;
+  if (dim == 3 && !C) return -6;
+  if (!X) return -7;
+  if (!Y || Y == X) return -8;
+  if (batch <= 0) return -9;
+  if (reps < 1) return -10;
+  auto run = [&]() -> int {
+    switch (mode * 2 + (dim - 2)) {
+      case 0: return kron2d_batched_f32(n, (const float*)A, (const float*)B, (const float*)X, (float*)Y, batch, stream);
+      case 1: return kron3d_batched_f32(n, (const float*)A, (const float*)B, (const float*)C, (const float*)X, (float*)Y, batch, stream);
+      case 2: return kron2d_batched_f64(n, (const double*)A, (const double*)B, (const double*)X, (double*)Y, batch, stream);
+      case 3: return kron3d_batched_f64(n, (const double*)A, (const double*)B, (const double*)C, (const double*)X, (double*)Y, batch, stream);
+      case 4: return kron2d_batched_f32_bf16x3(n, (const float*)A, (const float*)B, (const float*)X, (float*)Y, batch, stream);
+      case 5: return kron3d_batched_f32_bf16x3(n, (const float*)A, (const float*)B, (const float*)C, (const float*)X, (float*)Y, batch, stream);
+      case 6: return kron2d_batched_bf16(n, (const uint16_t*)A, (const uint16_t*)B, (const uint16_t*)X, (uint16_t*)Y, batch, stream);
+      default: return kron3d_batched_bf16(n, (const uint16_t*)A, (const uint16_t*)B, (const uint16_t*)C, (const uint16_t*)X, (uint16_t*)Y, batch, stream);
+    }
+  };
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return (int)e;
+  }
+  const int nvar = dim == 3 ? 9 : 4;
+  const int blocks[] = {0, 1, 2, 3, 4};
+  float best = 3.4e38f;
+  int bb = 0, bv = 0, rc = 0;
+  for (int v = 0; v < nvar && rc == 0; ++v) {
+    for (int b : blocks) {
+      kron::set_launch_shape(mode, dim, n, b, v);
+      if ((rc = run()) != 0) break;  // warm-up (code object load)
+      if ((e = hipEventRecord(e0, stream)) != hipSuccess) { rc = (int)e; break; }
+      for (int r = 0; r < reps && rc == 0; ++r) rc = run();
+      if (rc != 0) break;
+      if ((e = hipEventRecord(e1, stream)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess) {
+        rc = (int)e;
+        break;
+      }
+      float ms = 0.f;
+      if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) { rc = (int)e; break; }
+      ms /= (float)reps;
+      if (ms < best) { best = ms; bb = b; bv = v; }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != 0) {
+    kron::set_launch_shape(mode, dim, n, -1, 0);
+    return rc;
+  }
+  kron::set_launch_shape(mode, dim, n, bb, bv);
+  if (best_blocks) *best_blocks = bb;
+  if (best_variant) *best_variant = bv;
+  if (best_ms) *best_ms = best;
+  return 0;
 }
 
 int kron_get_launch(int mode, int dim, int n, int* blocks_per_cu, int* variant) {

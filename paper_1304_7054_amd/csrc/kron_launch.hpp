@@ -8,6 +8,7 @@
 #include <cstdint>
 
 #include "kron_kernels.hpp"
+#include "kron_staged.hpp"
 #include "kron_runtime.hpp"
 
 namespace kron {
@@ -65,7 +66,13 @@ void launch2d_v(int variant, const typename M::io_t* A, const typename M::io_t* 
   }
 }
 
-// 2-D variants: tiles kept in flight per wavefront, 0 -> 4, 1 -> 8, 2 -> 2.
+// Sizes that read their tiles through LDS (every n but 16; 3-D only for
+// elements of at most 4 bytes, whose slices fit 64 KiB per workgroup).
+template <class M, int N, int Dim>
+constexpr bool kStageable = N != 16 && (Dim == 2 || sizeof(typename M::io_t) <= 4);
+
+// 2-D variants: tiles kept in flight per wavefront, 0 -> 4, 1 -> 8, 2 -> 2;
+// 3 -> tiles staged through LDS (n != 16).
 template <class M, int N, bool kTrans>
 int launch2d_n(const typename M::io_t* A, const typename M::io_t* B, const typename M::io_t* X,
                typename M::io_t* Y, int64_t batch, hipStream_t stream, int mode) {
@@ -73,6 +80,15 @@ int launch2d_n(const typename M::io_t* A, const typename M::io_t* B, const typen
   constexpr int64_t ops = (int64_t)Geo<N>::Q * Geo<N>::Q;
   const int64_t ntiles = (batch + ops - 1) / ops;
   const LaunchShape sh = launch_shape(mode, 2, N);
+  if constexpr (kStageable<M, N, 2>) {
+    if (sh.variant == 3) {
+      auto k = kron2d_staged_kernel<M, N, kTrans>;
+      const int64_t waves = (ntiles + 3) / 4;
+      hipLaunchKernelGGL(k, dim3(grid_blocks(waves, occupancy_blocks(k), sh.blocks_per_cu)), dim3(kBlock), 0,
+                         stream, A, B, X, Y, batch, ntiles);
+      return 0;
+    }
+  }
   if constexpr (Geo<N>::kVec) {
     if (aligned_to(X, Mem<io_t>::kAlign) && aligned_to(Y, Mem<io_t>::kAlign)) {
       launch2d_v<M, N, kTrans, true>(sh.variant, A, B, X, Y, batch, ntiles, sh.blocks_per_cu, stream);
@@ -126,7 +142,9 @@ void launch3d_v(int variant, const typename M::io_t* A, const typename M::io_t* 
 // 3-D variants: 0 plain, 1 next tile prefetched, 2 contiguous 1 KiB rows
 // (operand slabs along the slow axis, a second lane-group exchange),
 // 3 = 1 + 2, 4/5 contiguous rows with a window of 2/4 slab loads in flight,
-// 6/7 = 4/5 with the next tile's first slabs requested before stage 3.
+// 6/7 = 4/5 with the next tile's first slabs requested before stage 3,
+// 8 = tiles staged through LDS (n != 16, elements of at most 4 bytes; other
+// sizes fall back to variant 0).
 template <class M, int N, bool kTrans>
 int launch3d_n(const typename M::io_t* A, const typename M::io_t* B, const typename M::io_t* C,
                const typename M::io_t* X, typename M::io_t* Y, int64_t batch, hipStream_t stream, int mode) {
@@ -134,6 +152,14 @@ int launch3d_n(const typename M::io_t* A, const typename M::io_t* B, const typen
   constexpr int64_t ops = (int64_t)Geo<N>::Q * Geo<N>::Q * Geo<N>::Q;
   const int64_t ntiles = (batch + ops - 1) / ops;
   const LaunchShape sh = launch_shape(mode, 3, N);
+  if constexpr (kStageable<M, N, 3>) {
+    if (sh.variant == 8) {
+      auto k = kron3d_staged_kernel<M, N, kTrans>;
+      hipLaunchKernelGGL(k, dim3(grid_blocks(ntiles, occupancy_blocks(k), sh.blocks_per_cu)), dim3(kBlock), 0,
+                         stream, A, B, C, X, Y, batch, ntiles);
+      return 0;
+    }
+  }
   if constexpr (Geo<N>::kVec) {
     if (aligned_to(X, Mem<io_t>::kAlign) && aligned_to(Y, Mem<io_t>::kAlign)) {
       launch3d_v<M, N, kTrans, true>(sh.variant, A, B, C, X, Y, batch, ntiles, sh.blocks_per_cu, stream);

@@ -227,8 +227,16 @@ def test_launch_variants_agree(mode, dim, n):
     want = _oracle(dim, n, gu.rounded_inputs(mode, mats), gu.rounded_inputs(mode, [X])[0], batch)
     refs = {}
     try:
-        for variant in ([0, 1, 2, 3, 4, 5, 6, 7] if dim == 3 else [0, 1, 2]):
-            order = (1 if variant >= 2 else 0) if dim == 3 else 0
+        for variant in ([0, 1, 2, 3, 4, 5, 6, 7, 8] if dim == 3 else [0, 1, 2, 3]):
+            # 3-D variants 2..7 and 8 (LDS-staged) contract C, B, A; 0 and 1
+            # contract C, A, B.  A variant a size cannot use runs variant 0.
+            stageable = n != 16 and mode != "f64"
+            if dim == 2:
+                order = 0
+            elif variant == 8:
+                order = 1 if stageable else 0
+            else:
+                order = 1 if variant >= 2 else 0
             for blocks in (0, 1):
                 kron.kron_set_launch(mcode, dim, n, blocks, variant)
                 got = gu.run(mode, dim, n, mats, X, batch)
