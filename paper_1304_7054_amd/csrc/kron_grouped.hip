@@ -26,6 +26,7 @@
 #include "kron_kernels.hpp"
 #include "kron_launch.hpp"
 #include "kron_runtime.hpp"
+#include "kron_staged.hpp"
 
 namespace kron {
 
@@ -64,95 +65,121 @@ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 // ---- device side ----------------------------------------------------------------
 
 // The item routines stay out of line: inlining all (mode, dim, n) paths into
-// the one kernel made the register allocator spill heavily.
+// the one kernel made the register allocator spill heavily.  Sizes other
+// than 16 go through the wavefront's LDS slice (kron_staged.hpp).
+constexpr int kGroupSlice = 4096 + 8;  // floats per wavefront: the largest 3-D tile
+
 template <class M, int N, bool kVec>
-__device__ __attribute__((noinline)) void run_item_2d(const GroupDesc& gd, const Item& it, int L, int g) {
-  using T = Tile2D<M, N, kVec, false>;
+__device__ __attribute__((noinline)) void run_item_2d(const GroupDesc& gd, const Item& it, int L, int g,
+                                                      float* slice) {
   using io_t = typename M::io_t;
   using acc_t = typename M::acc_t;
   const io_t* X = static_cast<const io_t*>(gd.X);
   io_t* Y = static_cast<io_t*>(gd.Y);
-  const T tile(static_cast<const io_t*>(gd.A), static_cast<const io_t*>(gd.B), L, g);
-  constexpr int kT = 4;
   const int64_t end = it.first_tile + it.ntiles;
-  for (int64_t base = it.first_tile; base < end; base += kT) {
-    acc_t x[kT];
+  constexpr int kT = 4;
+  if constexpr (N != 16) {
+    using S = Staged2D<M, N, false>;
+    static_assert(kT * S::kSlice <= kGroupSlice, "2-D slices exceed the wavefront's LDS");
+    const S st(static_cast<const io_t*>(gd.A), static_cast<const io_t*>(gd.B), L, g);
+    for (int64_t base = it.first_tile; base < end; base += kT)
+      staged2d_tiles<S, kT>(st, slice, X, Y, base, end, gd.count, threadIdx.x & 63);
+  } else {
+    using T = Tile2D<M, N, kVec, false>;
+    const T tile(static_cast<const io_t*>(gd.A), static_cast<const io_t*>(gd.B), L, g);
+    for (int64_t base = it.first_tile; base < end; base += kT) {
+      acc_t x[kT];
 #pragma unroll
-    for (int j = 0; j < kT; ++j) {
-      const int64_t t = base + j;
-      if (t < end) x[j] = tile.load(X + t * T::kOps * T::E, gd.count - t * T::kOps);
-      else x[j] = acc_t{0, 0, 0, 0};
-    }
+      for (int j = 0; j < kT; ++j) {
+        const int64_t t = base + j;
+        if (t < end) x[j] = tile.load(X + t * T::kOps * T::E, gd.count - t * T::kOps);
+        else x[j] = acc_t{0, 0, 0, 0};
+      }
 #pragma unroll
-    for (int j = 0; j < kT; ++j) x[j] = tile.compute(x[j]);
+      for (int j = 0; j < kT; ++j) x[j] = tile.compute(x[j]);
 #pragma unroll
-    for (int j = 0; j < kT; ++j) {
-      const int64_t t = base + j;
-      if (t < end) tile.finish(X + t * T::kOps * T::E, Y + t * T::kOps * T::E, gd.count - t * T::kOps, x[j]);
+      for (int j = 0; j < kT; ++j) {
+        const int64_t t = base + j;
+        if (t < end) tile.finish(X + t * T::kOps * T::E, Y + t * T::kOps * T::E, gd.count - t * T::kOps, x[j]);
+      }
     }
   }
 }
 
 template <class M, int N, bool kVec>
-__device__ __attribute__((noinline)) void run_item_3d(const GroupDesc& gd, const Item& it, int L, int g) {
-  using T = Tile3D<M, N, kVec, false, true>;
+__device__ __attribute__((noinline)) void run_item_3d(const GroupDesc& gd, const Item& it, int L, int g,
+                                                      float* slice) {
   using io_t = typename M::io_t;
   using acc_t = typename M::acc_t;
-  constexpr int kWindow = 2;
-  constexpr int64_t kStep = (int64_t)T::kOps * T::E;
   const io_t* X = static_cast<const io_t*>(gd.X);
   io_t* Y = static_cast<io_t*>(gd.Y);
-  const T tile(static_cast<const io_t*>(gd.A), static_cast<const io_t*>(gd.B), static_cast<const io_t*>(gd.C), L,
-               g);
+  const io_t* A = static_cast<const io_t*>(gd.A);
+  const io_t* B = static_cast<const io_t*>(gd.B);
+  const io_t* C = static_cast<const io_t*>(gd.C);
   const int64_t end = it.first_tile + it.ntiles;
-  for (int64_t t = it.first_tile; t < end; ++t) {
-    const io_t* Xt = X + t * kStep;
-    const int64_t rem = gd.count - t * T::kOps;
-    acc_t v[16];
+  if constexpr (N != 16) {
+    using S = Staged3D<M, N, false>;
+    static_assert(S::kSlice <= kGroupSlice, "3-D slice exceeds the wavefront's LDS");
+    const S st(A, B, C, L, g);
+    for (int64_t t = it.first_tile; t < end; ++t)
+      staged3d_tile(st, slice, X + t * S::kElems, Y + t * S::kElems, gd.count - t * S::kOps, threadIdx.x & 63);
+  } else {
+    using T = Tile3D<M, N, kVec, false, true>;
+    constexpr int kWindow = 2;
+    constexpr int64_t kStep = (int64_t)T::kOps * T::E;
+    const T tile(A, B, C, L, g);
+    for (int64_t t = it.first_tile; t < end; ++t) {
+      const io_t* Xt = X + t * kStep;
+      const int64_t rem = gd.count - t * T::kOps;
+      acc_t v[16];
 #pragma unroll
-    for (int b = 0; b < kWindow; ++b) tile.load_slab(Xt, rem, b, v[b]);
+      for (int b = 0; b < kWindow; ++b) tile.load_slab(Xt, rem, b, v[b]);
 #pragma unroll
-    for (int b = 0; b < 16; ++b) {
+      for (int b = 0; b < 16; ++b) {
+        __builtin_amdgcn_sched_barrier(0);
+        tile.stage12(v[b]);
+        if (b + kWindow < 16) tile.load_slab(Xt, rem, b + kWindow, v[b + kWindow]);
+      }
       __builtin_amdgcn_sched_barrier(0);
-      tile.stage12(v[b]);
-      if (b + kWindow < 16) tile.load_slab(Xt, rem, b + kWindow, v[b + kWindow]);
+      tile.stage3(v);
+      tile.finish(Xt, Y + t * kStep, rem, v);
     }
-    __builtin_amdgcn_sched_barrier(0);
-    tile.stage3(v);
-    tile.finish(Xt, Y + t * kStep, rem, v);
   }
 }
 
 template <class M>
-__device__ __forceinline__ void run_item(const GroupDesc& gd, const Item& it, int L, int g) {
-#define KRON_G_CASE(NN)                                                    \
-  case NN:                                                                 \
-    if (gd.dim == 2) {                                                     \
-      if (Geo<NN>::kVec && gd.vec) run_item_2d<M, NN, Geo<NN>::kVec>(gd, it, L, g); \
-      else run_item_2d<M, NN, false>(gd, it, L, g);                        \
-    } else {                                                               \
-      if (Geo<NN>::kVec && gd.vec) run_item_3d<M, NN, Geo<NN>::kVec>(gd, it, L, g); \
-      else run_item_3d<M, NN, false>(gd, it, L, g);                        \
-    }                                                                      \
+__device__ __forceinline__ void run_item(const GroupDesc& gd, const Item& it, int L, int g, float* slice) {
+#define KRON_G_CASE(NN)                                                                  \
+  case NN:                                                                               \
+    if (gd.dim == 2) {                                                                   \
+      if (NN == 16 && gd.vec) run_item_2d<M, NN, NN == 16>(gd, it, L, g, slice);         \
+      else run_item_2d<M, NN, false>(gd, it, L, g, slice);                               \
+    } else {                                                                             \
+      if (NN == 16 && gd.vec) run_item_3d<M, NN, NN == 16>(gd, it, L, g, slice);         \
+      else run_item_3d<M, NN, false>(gd, it, L, g, slice);                               \
+    }                                                                                    \
     break;
   switch (gd.n) { KRON_N_CASES(KRON_G_CASE) }
 #undef KRON_G_CASE
 }
 
-__global__ __launch_bounds__(kBlock) void kron_grouped_kernel(const uint8_t* __restrict__ ws) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) void kron_grouped_kernel(
+    const uint8_t* __restrict__ ws) {
   const Header* h = reinterpret_cast<const Header*>(ws);
   const GroupDesc* groups = reinterpret_cast<const GroupDesc*>(ws + h->groups_off);
   const int32_t* starts = reinterpret_cast<const int32_t*>(ws + h->starts_off);
   const Item* items = reinterpret_cast<const Item*>(ws + h->items_off);
+  __shared__ __attribute__((aligned(16))) float slices[kBlock / kWave][kGroupSlice];
   const int l = threadIdx.x & 63, L = l & 15, g = l >> 4;
+  float* slice = slices[threadIdx.x >> 6];
   const int wave = (int)(((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6);
   if (wave >= h->nwaves) return;
   const int i1 = starts[wave + 1];
   for (int i = starts[wave]; i < i1; ++i) {
     const Item it = items[i];
     const GroupDesc gd = groups[it.group];
-    if (gd.mode == KRON_MODE_BF16X3) run_item<ModeBF16x3>(gd, it, L, g);
-    else run_item<ModeF32>(gd, it, L, g);
+    if (gd.mode == KRON_MODE_BF16X3) run_item<ModeBF16x3>(gd, it, L, g, slice);
+    else run_item<ModeF32>(gd, it, L, g, slice);
   }
 }
 

@@ -156,10 +156,53 @@ struct Staged3D {
   }
 };
 
-// One tile per step.  Packed tiles (several operands) whose result holds a
-// non-finite value are redone one operand at a time: the slice is zeroed,
-// only operand o is copied in (at its own place), the same code runs, and
-// only operand o is copied out, so IEEE propagation stays inside operand o.
+// One tile through an LDS slice of at least S::kSlice elements.  Packed
+// tiles (several operands) whose result holds a non-finite value are redone
+// one operand at a time: the slice is zeroed, only operand o is copied in (at
+// its own place), the same code runs, and only operand o is copied out, so
+// IEEE propagation stays inside operand o.
+template <class S>
+__device__ __forceinline__ void staged3d_tile(const S& st, typename S::io_t* lds, const typename S::io_t* Xt,
+                                              typename S::io_t* Yt, int64_t rem, int l) {
+  using acc_t = typename S::acc_t;
+  const int nops = (int)(rem < S::kOps ? rem : S::kOps);
+  for (int o = -1;;) {
+    // o < 0: the whole tile; o >= 0: operand o alone
+    const int first = o < 0 ? 0 : o * S::E;
+    const int count = o < 0 ? nops * S::E : S::E;
+    wave_sync_lds();  // the previous copy-out has read the slice
+    if (o >= 0) zero_fill(lds, 0, S::kElems, l);
+    else zero_fill(lds, count, S::kElems, l);
+    wave_sync_lds();
+    copy_in(Xt + first, lds + first, count, l);
+    wave_sync_lds();
+    acc_t v[16];
+#pragma unroll
+    for (int a = 0; a < 16; ++a) {
+      v[a] = st.read(lds, a);
+      st.tile.stage12(v[a]);
+    }
+    st.tile.stage3(v);
+    if constexpr (S::kOps > 1) {
+      if (o < 0) {
+        bool fin = true;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) fin = fin && all_finite(v[i]);
+        if (__any(!fin)) {
+          o = 0;
+          continue;
+        }
+      }
+    }
+    wave_sync_lds();  // every lane has read its slots
+#pragma unroll
+    for (int i = 0; i < 16; ++i) st.write(lds, i, v[i]);
+    wave_sync_lds();
+    copy_out(Yt + first, lds + first, count, l);
+    if (o < 0 || ++o >= nops) break;
+  }
+}
+
 template <class M, int N, bool kTrans>
 __global__ __launch_bounds__(kBlock) void kron3d_staged_kernel(const typename M::io_t* __restrict__ A,
                                                                const typename M::io_t* __restrict__ B,
@@ -169,54 +212,14 @@ __global__ __launch_bounds__(kBlock) void kron3d_staged_kernel(const typename M:
                                                                int64_t ntiles) {
   using S = Staged3D<M, N, kTrans>;
   using io_t = typename M::io_t;
-  using acc_t = typename M::acc_t;
   __shared__ __attribute__((aligned(16))) io_t slices[kBlock / kWave][S::kSlice];
   const int l = threadIdx.x & 63, L = l & 15, g = l >> 4;
   io_t* lds = slices[threadIdx.x >> 6];
   const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * kBlock) >> 6;
   const S st(A, B, C, L, g);
-  for (int64_t t = wave; t < ntiles; t += nwaves) {
-    const int64_t rem = batch - t * S::kOps;
-    const int nops = (int)(rem < S::kOps ? rem : S::kOps);
-    const io_t* Xt = X + t * S::kElems;
-    io_t* Yt = Y + t * S::kElems;
-    for (int o = -1;;) {
-      // o < 0: the whole tile; o >= 0: operand o alone
-      const int first = o < 0 ? 0 : o * S::E;
-      const int count = o < 0 ? nops * S::E : S::E;
-      wave_sync_lds();  // the previous copy-out has read the slice
-      if (o >= 0) zero_fill(lds, 0, S::kElems, l);
-      else zero_fill(lds, count, S::kElems, l);
-      wave_sync_lds();
-      copy_in(Xt + first, lds + first, count, l);
-      wave_sync_lds();
-      acc_t v[16];
-#pragma unroll
-      for (int a = 0; a < 16; ++a) {
-        v[a] = st.read(lds, a);
-        st.tile.stage12(v[a]);
-      }
-      st.tile.stage3(v);
-      if constexpr (S::kOps > 1) {
-        if (o < 0) {
-          bool fin = true;
-#pragma unroll
-          for (int i = 0; i < 16; ++i) fin = fin && all_finite(v[i]);
-          if (__any(!fin)) {
-            o = 0;
-            continue;
-          }
-        }
-      }
-      wave_sync_lds();  // every lane has read its slots
-#pragma unroll
-      for (int i = 0; i < 16; ++i) st.write(lds, i, v[i]);
-      wave_sync_lds();
-      copy_out(Yt + first, lds + first, count, l);
-      if (o < 0 || ++o >= nops) break;
-    }
-  }
+  for (int64_t t = wave; t < ntiles; t += nwaves)
+    staged3d_tile(st, lds, X + t * S::kElems, Y + t * S::kElems, batch - t * S::kOps, l);
 }
 
 // ---- 2-D (X: L on the slow axis, slots 4g + s on the fast axis; Y: L on the
@@ -257,8 +260,66 @@ struct Staged2D {
   }
 };
 
-// kT tiles per wavefront step (one slice each) keep a few KiB in flight;
-// a packed tile with a non-finite result is redone per operand as in 3-D.
+// kT consecutive tiles (from tile t0, at most `last` - t0 of them) through
+// kT LDS slices of S::kSlice elements each; a packed tile with a non-finite
+// result is redone per operand as in 3-D.
+template <class S, int kT>
+__device__ __forceinline__ void staged2d_tiles(const S& st, typename S::io_t* slices, const typename S::io_t* X,
+                                               typename S::io_t* Y, int64_t t0, int64_t last, int64_t batch,
+                                               int l) {
+  using io_t = typename S::io_t;
+  using acc_t = typename S::acc_t;
+  int nops[kT];
+#pragma unroll
+  for (int j = 0; j < kT; ++j) {
+    const int64_t t = t0 + j;
+    const int64_t rem = t < last ? batch - t * S::kOps : 0;
+    nops[j] = (int)(rem < S::kOps ? rem : S::kOps);
+  }
+  wave_sync_lds();
+#pragma unroll
+  for (int j = 0; j < kT; ++j) zero_fill(slices + j * S::kSlice, nops[j] * S::E, S::kElems, l);
+#pragma unroll
+  for (int j = 0; j < kT; ++j)
+    if (nops[j] > 0) copy_in(X + (t0 + j) * S::kElems, slices + j * S::kSlice, nops[j] * S::E, l);
+  wave_sync_lds();
+  acc_t v[kT];
+#pragma unroll
+  for (int j = 0; j < kT; ++j) v[j] = st.tile.compute(st.read(slices + j * S::kSlice));
+  bool bad[kT];
+#pragma unroll
+  for (int j = 0; j < kT; ++j) bad[j] = S::kOps > 1 && nops[j] > 0 && __any(!all_finite(v[j]));
+  wave_sync_lds();
+#pragma unroll
+  for (int j = 0; j < kT; ++j)
+    if (!bad[j]) st.write(slices + j * S::kSlice, v[j]);
+  wave_sync_lds();
+#pragma unroll
+  for (int j = 0; j < kT; ++j)
+    if (nops[j] > 0 && !bad[j]) copy_out(Y + (t0 + j) * S::kElems, slices + j * S::kSlice, nops[j] * S::E, l);
+  if constexpr (S::kOps > 1) {
+    for (int j = 0; j < kT; ++j) {
+      if (!bad[j]) continue;
+      io_t* sl = slices + j * S::kSlice;
+      const io_t* Xt = X + (t0 + j) * S::kElems;
+      io_t* Yt = Y + (t0 + j) * S::kElems;
+      // this tile's results were not written back: redo it operand by operand
+      for (int o = 0; o < nops[j]; ++o) {
+        wave_sync_lds();
+        zero_fill(sl, 0, S::kElems, l);
+        wave_sync_lds();
+        copy_in(Xt + o * S::E, sl + o * S::E, S::E, l);
+        wave_sync_lds();
+        const acc_t y = st.tile.compute(st.read(sl));
+        wave_sync_lds();
+        st.write(sl, y);
+        wave_sync_lds();
+        copy_out(Yt + o * S::E, sl + o * S::E, S::E, l);
+      }
+    }
+  }
+}
+
 template <class M, int N, bool kTrans>
 __global__ __launch_bounds__(kBlock) void kron2d_staged_kernel(const typename M::io_t* __restrict__ A,
                                                                const typename M::io_t* __restrict__ B,
@@ -267,63 +328,15 @@ __global__ __launch_bounds__(kBlock) void kron2d_staged_kernel(const typename M:
                                                                int64_t ntiles) {
   using S = Staged2D<M, N, kTrans>;
   using io_t = typename M::io_t;
-  using acc_t = typename M::acc_t;
   constexpr int kT = 4;
-  __shared__ __attribute__((aligned(16))) io_t slices[kBlock / kWave][kT][S::kSlice];
+  __shared__ __attribute__((aligned(16))) io_t slices[kBlock / kWave][kT * S::kSlice];
   const int l = threadIdx.x & 63, L = l & 15, g = l >> 4;
-  auto& mine = slices[threadIdx.x >> 6];
+  io_t* mine = slices[threadIdx.x >> 6];
   const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * kBlock) >> 6;
   const S st(A, B, L, g);
-  for (int64_t base = wave * kT; base < ntiles; base += nwaves * kT) {
-    int nops[kT];
-#pragma unroll
-    for (int j = 0; j < kT; ++j) {
-      const int64_t t = base + j;
-      const int64_t rem = t < ntiles ? batch - t * S::kOps : 0;
-      nops[j] = (int)(rem < S::kOps ? rem : S::kOps);
-    }
-    wave_sync_lds();
-#pragma unroll
-    for (int j = 0; j < kT; ++j) zero_fill(mine[j], nops[j] * S::E, S::kElems, l);
-#pragma unroll
-    for (int j = 0; j < kT; ++j)
-      if (nops[j] > 0) copy_in(X + (base + j) * S::kElems, mine[j], nops[j] * S::E, l);
-    wave_sync_lds();
-    acc_t v[kT];
-#pragma unroll
-    for (int j = 0; j < kT; ++j) v[j] = st.tile.compute(st.read(mine[j]));
-    bool bad[kT];
-#pragma unroll
-    for (int j = 0; j < kT; ++j) bad[j] = S::kOps > 1 && nops[j] > 0 && __any(!all_finite(v[j]));
-    wave_sync_lds();
-#pragma unroll
-    for (int j = 0; j < kT; ++j)
-      if (!bad[j]) st.write(mine[j], v[j]);
-    wave_sync_lds();
-#pragma unroll
-    for (int j = 0; j < kT; ++j)
-      if (nops[j] > 0 && !bad[j]) copy_out(Y + (base + j) * S::kElems, mine[j], nops[j] * S::E, l);
-    if constexpr (S::kOps > 1) {
-      for (int j = 0; j < kT; ++j) {
-        if (!bad[j]) continue;
-        const io_t* Xt = X + (base + j) * S::kElems;
-        io_t* Yt = Y + (base + j) * S::kElems;
-        for (int o = 0; o < nops[j]; ++o) {
-          wave_sync_lds();
-          zero_fill(mine[j], 0, S::kElems, l);
-          wave_sync_lds();
-          copy_in(Xt + o * S::E, mine[j] + o * S::E, S::E, l);
-          wave_sync_lds();
-          const acc_t y = st.tile.compute(st.read(mine[j]));
-          wave_sync_lds();
-          st.write(mine[j], y);
-          wave_sync_lds();
-          copy_out(Yt + o * S::E, mine[j] + o * S::E, S::E, l);
-        }
-      }
-    }
-  }
+  for (int64_t base = wave * kT; base < ntiles; base += nwaves * kT)
+    staged2d_tiles<S, kT>(st, mine, X, Y, base, ntiles, batch, l);
 }
 
 }  // namespace kron
