@@ -23,6 +23,7 @@
 #pragma once
 
 #include "kron_kernels.hpp"
+#include "kron_staged.hpp"
 
 namespace kron {
 
@@ -186,6 +187,68 @@ struct Grad2D {
 
 constexpr int kGradBlock = 256;
 
+// FP32: X and dY of a tile are copied once into the wavefront's LDS (16-byte
+// coalesced loads), and the six operand layouts the three gradients need are
+// read from there (one address register per row-group slot plus immediate
+// offsets).  FP64 tiles would not fit, so FP64 reads global memory directly.
+template <class M, int N>
+constexpr bool kGradStaged = sizeof(typename M::io_t) == 4;
+
+template <class M, int N>
+struct Grad3DStaged {
+  using io_t = typename M::io_t;
+  using acc_t = typename M::acc_t;
+  using fac_t = typename M::fac_t;
+  using G = TileGeom<N, 3>;
+  static constexpr int Q = Geo<N>::Q;
+  static constexpr int kOps = Q * Q * Q;
+  static constexpr int E = G::E;
+  static constexpr int kElems = kOps * E;
+  static constexpr int kSlice = (kElems + 7) / 8 * 8;
+  fac_t fA, fB, fC;
+  int L, g;
+
+  __device__ __forceinline__ Grad3DStaged(const io_t* A, const io_t* B, const io_t* C, int L_, int g_)
+      : L(L_), g(g_) {
+    fA = M::template load_fac<N, false>(A, L, g, 0);
+    fB = M::template load_fac<N, false>(B, L, g, 0);
+    fC = M::template load_fac<N, false>(C, L, g, 0);
+  }
+
+  template <int SAX>
+  __device__ __forceinline__ static acc_t read(const io_t* lds, const LaneSlots<N, 3>& ls, int slab) {
+    AxisPart<N, E> ps(slab, G::stride(SAX), G::opmul(SAX));
+    acc_t v = acc_t{0, 0, 0, 0};
+    if (!ps.valid) return v;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const float x = lds[ls.base[s] + ps.off];
+      v[s] = ls.ok[s] ? x : 0.f;
+    }
+    return v;
+  }
+
+  // F = 0 (dA), 1 (dB), 2 (dC); same layouts as Grad3D::tile.
+  template <int F>
+  __device__ __forceinline__ void tile(const io_t* ldsX, const io_t* ldsY, acc_t& acc) const {
+    constexpr int lax = F;
+    constexpr int gax = F == 2 ? 1 : 2;
+    constexpr int sax = F == 0 ? 1 : 0;
+    constexpr int ygax = F == 0 ? 1 : 0;
+    constexpr int ysax = F == 2 ? 1 : 2;
+    const LaneSlots<N, 3> lx(L, lax, g, gax, false);
+    acc_t t[16];
+#pragma unroll
+    for (int s = 0; s < 16; ++s) t[s] = M::db(F == 2 ? fB : fC, read<sax>(ldsX, lx, s));
+    Grad3D<M, N>::swap_rows_slabs(t);
+#pragma unroll
+    for (int s = 0; s < 16; ++s) t[s] = M::db(F == 0 ? fB : fA, t[s]);
+    const LaneSlots<N, 3> ly(L, lax, g, ygax, M::drow(0, 1) != 1);
+#pragma unroll
+    for (int s = 0; s < 16; ++s) acc = mma_data<M>(read<ysax>(ldsY, ly, s), t[s], acc);
+  }
+};
+
 // Partials: ws[(wave * 3 + f) * 256 + row * 16 + col] holds wavefront `wave`'s
 // 16 x 16 tile of factor f's gradient (row = drow(g, r), col = L).
 template <class M, int N, int Dim>
@@ -196,13 +259,33 @@ __global__ __launch_bounds__(kGradBlock) void kron_grad_partial_kernel(
     int64_t ntiles, int which) {
   using acc_t = typename M::acc_t;
   using T = typename M::elem_t;
+  using io_t = typename M::io_t;
   const int l = threadIdx.x & 63, L = l & 15, g = l >> 4;
   const int64_t wave = ((int64_t)blockIdx.x * kGradBlock + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * kGradBlock) >> 6;
   acc_t acc[3];
 #pragma unroll
   for (int f = 0; f < 3; ++f) acc[f] = acc_t{0, 0, 0, 0};
-  if constexpr (Dim == 3) {
+  if constexpr (Dim == 3 && kGradStaged<M, N>) {
+    using GS = Grad3DStaged<M, N>;
+    __shared__ __attribute__((aligned(16))) io_t slices[kGradBlock / kWave][2][GS::kSlice];
+    io_t* ldsX = slices[threadIdx.x >> 6][0];
+    io_t* ldsY = slices[threadIdx.x >> 6][1];
+    const GS gr(A, B, C, L, g);
+    for (int64_t t = wave; t < ntiles; t += nwaves) {
+      const int64_t rem = batch - t * GS::kOps;
+      const int count = (int)((rem < GS::kOps ? rem : GS::kOps) * GS::E);
+      wave_sync_lds();
+      zero_fill(ldsX, count, GS::kElems, l);
+      zero_fill(ldsY, count, GS::kElems, l);
+      copy_in(X + t * GS::kElems, ldsX, count, l);
+      copy_in(dY + t * GS::kElems, ldsY, count, l);
+      wave_sync_lds();
+      if (which & 1) gr.template tile<0>(ldsX, ldsY, acc[0]);
+      if (which & 2) gr.template tile<1>(ldsX, ldsY, acc[1]);
+      if (which & 4) gr.template tile<2>(ldsX, ldsY, acc[2]);
+    }
+  } else if constexpr (Dim == 3) {
     using G3 = Grad3D<M, N>;
     constexpr int64_t step = (int64_t)G3::kOps * N * N * N;
     const G3 gr(A, B, C, L, g);
@@ -229,7 +312,7 @@ __global__ __launch_bounds__(kGradBlock) void kron_grad_partial_kernel(
 }
 
 // dM(i, j) = sum over wavefronts (in order) and over the Q diagonal blocks of
-// the partial tiles; one thread per entry of each requested factor; sums in
+// the partial tiles (logical index q*n + i sits in slot slot_of(q*n + i)); one thread per entry of each requested factor; sums in
 // double.  Output column-major (i + n*j).
 template <typename io_t, typename T, int N>
 __global__ __launch_bounds__(kGradBlock) void kron_grad_reduce_kernel(const T* __restrict__ ws, int64_t nwaves,
@@ -245,7 +328,7 @@ __global__ __launch_bounds__(kGradBlock) void kron_grad_reduce_kernel(const T* _
     for (int64_t w = 0; w < nwaves; ++w) {
       const T* tile = ws + (w * 3 + f) * 256;
 #pragma unroll
-      for (int q = 0; q < Q; ++q) s += (double)tile[(q * N + i) * 16 + (q * N + j)];
+      for (int q = 0; q < Q; ++q) s += (double)tile[slot_of<N>(q * N + i) * 16 + slot_of<N>(q * N + j)];
     }
     out[i + N * j] = (io_t)s;
   }

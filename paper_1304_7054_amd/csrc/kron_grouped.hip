@@ -138,7 +138,7 @@ __device__ __attribute__((noinline)) void run_item_3d(const GroupDesc& gd, const
       for (int b = 0; b < 16; ++b) {
         __builtin_amdgcn_sched_barrier(0);
         tile.stage12(v[b]);
-        if (b + kWindow < 16) tile.load_slab(Xt, rem, b + kWindow, v[b + kWindow]);
+        if (b + kWindow < 16) tile.load_slab(Xt, rem, b + kWindow, v[b + kWindow]);  // n == 16: all live
       }
       __builtin_amdgcn_sched_barrier(0);
       tile.stage3(v);

@@ -152,7 +152,10 @@ struct Tile2D {
     return x;
   }
 
-  __device__ __forceinline__ acc_t compute(const acc_t& x) const { return M::da(fA, M::da_in(fB, x)); }
+  static constexpr int kS = Geo<N>::kSteps;
+  __device__ __forceinline__ acc_t compute(const acc_t& x) const {
+    return M::template da<kS>(fA, M::template da_in<kS>(fB, x));
+  }
 
   __device__ __forceinline__ void store(io_t* Yt, int64_t rem, const acc_t& y, int only = -1) const {
     if constexpr (N == 16 && kStoreVec) {
@@ -261,14 +264,18 @@ struct Tile3D {
     for (int s = 0; s < 4; ++s) z[s] = t[4 * gi + s][ri];
   }
 
+  static constexpr int kS = Geo<N>::kSteps;
+  // slabs whose slot holds no element stay zero and are not computed
+  __device__ static constexpr bool live(int slab) { return slot_live<N>(slab); }
+
   // Stages 1 and 2 touch one slab at a time.
   __device__ __forceinline__ void stage12(acc_t& v) const {
     if constexpr (kContig) {
       // slab a of X(a, b = slot L, c = slots 4g+s): contract c (rows b, column k), then b (rows k, column j)
-      v = M::da(fB, M::da_in(fC, v));
+      v = M::template da<kS>(fB, M::template da_in<kS>(fC, v));
     } else {
       // slab b of X(a = slot L, b, c = slots 4g+s): contract c (rows a, column k), then a (rows i, column k)
-      v = M::db(fA, M::da_in(fC, v));
+      v = M::template db<kS>(fA, M::template da_in<kS>(fC, v));
     }
   }
 
@@ -280,9 +287,13 @@ struct Tile3D {
     if constexpr (kContig) {
 #pragma unroll
       for (int k = 0; k < 16; ++k) {
+        if (!live(k)) {
+          u[k] = acc_t{0, 0, 0, 0};
+          continue;
+        }
         acc_t z;
         regather(t, k, z);
-        u[k] = M::db(fA, z);          // contract a: rows i, column j, slab k
+        u[k] = M::template db<kS>(fA, z);  // contract a: rows i, column j, slab k
       }
       exchange_groups_slabs(u);       // -> slab i, slots k on (g, s)
 #pragma unroll
@@ -290,9 +301,13 @@ struct Tile3D {
     } else {
 #pragma unroll
       for (int i = 0; i < 16; ++i) {
+        if (!live(i)) {
+          u[i] = acc_t{0, 0, 0, 0};
+          continue;
+        }
         acc_t z;
         regather(t, i, z);
-        u[i] = M::da(fB, z);          // contract b: rows k, column j, slab i
+        u[i] = M::template da<kS>(fB, z);  // contract b: rows k, column j, slab i
       }
 #pragma unroll
       for (int i = 0; i < 16; ++i) t[i] = u[i];
@@ -302,7 +317,8 @@ struct Tile3D {
   // t: loaded slabs in, results (slab i) out
   __device__ __forceinline__ void compute(acc_t (&t)[16]) const {
 #pragma unroll
-    for (int b = 0; b < 16; ++b) stage12(t[b]);
+    for (int b = 0; b < 16; ++b)
+      if (live(b)) stage12(t[b]);
     stage3(t);
   }
 
@@ -425,7 +441,7 @@ __global__ __launch_bounds__(kBlock) void kron3d_kernel(const typename M::io_t* 
 #pragma unroll
       for (int b = 0; b < 16; ++b) {
         __builtin_amdgcn_sched_barrier(0);
-        tile.stage12(v[b]);
+        if (T::live(b)) tile.stage12(v[b]);
         if (b + kWindow < 16) tile.load_slab(Xt, rem, b + kWindow, v[b + kWindow]);
       }
       __builtin_amdgcn_sched_barrier(0);

@@ -22,10 +22,11 @@ __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// element in memory -> compute type (bf16 bits -> FP32; FP32 and FP64 as they are)
 template <typename io_t>
-__device__ __forceinline__ float widen(io_t v) {
+__device__ __forceinline__ auto widen(io_t v) {
   if constexpr (sizeof(io_t) == 2) return from_bf16(bits_to_bf16(v));
-  else return (float)v;
+  else return v;
 }
 
 template <typename io_t, typename T>
@@ -141,8 +142,8 @@ struct Staged3D {
     if (!ps.valid) return v;
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-      const float x = widen(lds[ls.base[s] + ps.off]);
-      v[s] = ls.ok[s] ? x : 0.f;
+      const auto x = widen(lds[ls.base[s] + ps.off]);
+      v[s] = ls.ok[s] ? x : decltype(x)(0);
     }
     return v;
   }
@@ -180,7 +181,7 @@ __device__ __forceinline__ void staged3d_tile(const S& st, typename S::io_t* lds
 #pragma unroll
     for (int a = 0; a < 16; ++a) {
       v[a] = st.read(lds, a);
-      st.tile.stage12(v[a]);
+      if (S::Tile::live(a)) st.tile.stage12(v[a]);
     }
     st.tile.stage3(v);
     if constexpr (S::kOps > 1) {
@@ -247,8 +248,8 @@ struct Staged2D {
     acc_t v;
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-      const float x = widen(lds[in.base[s]]);
-      v[s] = in.ok[s] ? x : 0.f;
+      const auto x = widen(lds[in.base[s]]);
+      v[s] = in.ok[s] ? x : decltype(x)(0);
     }
     return v;
   }

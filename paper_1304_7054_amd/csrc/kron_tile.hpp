@@ -46,7 +46,14 @@ struct Geo {
   static_assert(N >= 1 && N <= 16, "n must be in 1..16");
   static constexpr int Q = kSlots / N;   // operands packed per axis
   static constexpr int U = Q * N;        // used slots per axis
-  static constexpr bool kVec = (N % 4) == 0;  // 4 consecutive slots = 4 consecutive elements
+  // When fewer than 16 slots hold data, logical index u sits in slot
+  // 4 * (u % 4) + u / 4 (row group u % 4, register u / 4): the used slots
+  // then fill the first kSteps contraction steps, and the remaining steps
+  // (all zero) are skipped.  Every axis, the data and the factor tiles use the
+  // same placement, so the contractions are unchanged.
+  static constexpr bool kPerm = U < 16;
+  static constexpr int kSteps = kPerm ? (U + 3) / 4 : 4;
+  static constexpr bool kVec = (N % 4) == 0 && !kPerm;  // 4 consecutive slots = 4 consecutive elements
 };
 
 // slot -> (packed-operand index along the axis, index inside the operand)
@@ -54,8 +61,25 @@ template <int N>
 struct Slot {
   int sub, idx;
   bool valid;
-  __device__ __forceinline__ explicit Slot(int s) : sub(s / N), idx(s % N), valid(s < Geo<N>::U) {}
+  __device__ __forceinline__ explicit Slot(int s) {
+    const int u = Geo<N>::kPerm ? 4 * (s % 4) + s / 4 : s;
+    sub = u / N;
+    idx = u % N;
+    valid = u < Geo<N>::U;
+  }
 };
+
+// logical index u (0 <= u < U) -> its slot (the inverse of Slot: the
+// placement is its own inverse)
+template <int N>
+__device__ __forceinline__ constexpr int slot_of(int u) {
+  return Geo<N>::kPerm ? 4 * (u % 4) + u / 4 : u;
+}
+
+template <int N>
+__device__ __forceinline__ constexpr bool slot_live(int s) {
+  return (Geo<N>::kPerm ? 4 * (s % 4) + s / 4 : s) < Geo<N>::U;
+}
 
 // ---- bf16 helpers ------------------------------------------------------------
 
@@ -140,19 +164,22 @@ struct ModeF32 {
     for (int s = 0; s < 4; ++s) f[s] = tile_entry<N, kTrans>(M, L, kmap == 0 ? 4 * g + s : drow(g, s));
     return f;
   }
+  template <int kSteps = 4>
   __device__ static acc_t da(const fac_t& f, const acc_t& x) {
     acc_t c = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int s = 0; s < 4; ++s) c = mfma_f32(x[s], f[s], c);
+    for (int s = 0; s < kSteps; ++s) c = mfma_f32(x[s], f[s], c);
     return c;
   }
+  template <int kSteps = 4>
   __device__ static acc_t db(const fac_t& f, const acc_t& x) {
     acc_t c = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int s = 0; s < 4; ++s) c = mfma_f32(f[s], x[s], c);
+    for (int s = 0; s < kSteps; ++s) c = mfma_f32(f[s], x[s], c);
     return c;
   }
-  __device__ static acc_t da_in(const fac_t& f, const acc_t& x) { return da(f, x); }
+  template <int kSteps = 4>
+  __device__ static acc_t da_in(const fac_t& f, const acc_t& x) { return da<kSteps>(f, x); }
   __device__ static acc_t to_acc(const f32x4& v) { return v; }
 };
 
@@ -170,19 +197,32 @@ struct ModeF64 {
     for (int s = 0; s < 4; ++s) f[s] = tile_entry<N, kTrans>(M, L, kmap == 0 ? 4 * g + s : drow(g, s));
     return f;
   }
+  // An FP64 accumulator holds rows g + 4r, so when it feeds the next stage
+  // step s contracts slots 4s..4s+3, which under the placement of Geo hold
+  // logical indices s, s+4, s+8, s+12: every step can hold data, and da/db
+  // always take all four.  Only the first stage, fed in slot order 4g + s
+  // (step s = logical 4s..4s+3), skips the empty steps.
+  template <int kSteps = 4>
   __device__ static acc_t da(const fac_t& f, const acc_t& x) {
     acc_t c = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int s = 0; s < 4; ++s) c = mfma_f64(x[s], f[s], c);
     return c;
   }
+  template <int kSteps = 4>
   __device__ static acc_t db(const fac_t& f, const acc_t& x) {
     acc_t c = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int s = 0; s < 4; ++s) c = mfma_f64(f[s], x[s], c);
     return c;
   }
-  __device__ static acc_t da_in(const fac_t& f, const acc_t& x) { return da(f, x); }
+  template <int kSteps = 4>
+  __device__ static acc_t da_in(const fac_t& f, const acc_t& x) {
+    acc_t c = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < kSteps; ++s) c = mfma_f64(x[s], f[s], c);
+    return c;
+  }
 };
 
 // bf16x3: every FP32 value v is split as hi + lo; a product v*m is taken as
@@ -212,6 +252,7 @@ struct ModeBF16x3 {
     for (int e = 0; e < 4; ++e) zero[e] = to_bf16(0.f);
     return fac_t{cat8(lo, hi), cat8(hi, zero)};
   }
+  template <int kSteps = 4>
   __device__ static acc_t da(const fac_t& f, const acc_t& x) {
     bf16x4 hi, lo;
     split4(x, hi, lo);
@@ -220,6 +261,7 @@ struct ModeBF16x3 {
     c = mfma_bf16_k32(d, f.small, c);
     return mfma_bf16_k32(d, f.big, c);
   }
+  template <int kSteps = 4>
   __device__ static acc_t db(const fac_t& f, const acc_t& x) {
     bf16x4 hi, lo;
     split4(x, hi, lo);
@@ -228,6 +270,7 @@ struct ModeBF16x3 {
     c = mfma_bf16_k32(f.small, d, c);
     return mfma_bf16_k32(f.big, d, c);
   }
+  template <int kSteps = 4>
   __device__ static acc_t da_in(const fac_t& f, const acc_t& x) { return da(f, x); }
 };
 
@@ -254,12 +297,14 @@ struct ModeBF16 {
     }
     return f;
   }
+  template <int kSteps = 4>
   __device__ static acc_t da(const fac_t& f, const acc_t& x) {
     bf16x4 hi, lo;
     split4(x, hi, lo);
     acc_t c = {0.f, 0.f, 0.f, 0.f};
     return mfma_bf16_k32(cat8(hi, lo), cat8(f, f), c);
   }
+  template <int kSteps = 4>
   __device__ static acc_t db(const fac_t& f, const acc_t& x) {
     bf16x4 hi, lo;
     split4(x, hi, lo);
@@ -267,6 +312,7 @@ struct ModeBF16 {
     return mfma_bf16_k32(cat8(f, f), cat8(hi, lo), c);
   }
   // first stage: x holds exact bf16 values widened to FP32
+  template <int kSteps = 4>
   __device__ static acc_t da_in(const fac_t& f, const acc_t& x) {
     bf16x4 h;
 #pragma unroll
