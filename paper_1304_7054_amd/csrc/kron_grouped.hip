@@ -77,14 +77,14 @@ __device__ __attribute__((noinline)) void run_item_2d(const GroupDesc& gd, const
   const io_t* X = static_cast<const io_t*>(gd.X);
   io_t* Y = static_cast<io_t*>(gd.Y);
   const int64_t end = it.first_tile + it.ntiles;
-  constexpr int kT = 4;
   if constexpr (N != 16) {
     using S = Staged2D<M, N, false>;
-    static_assert(kT * S::kSlice <= kGroupSlice, "2-D slices exceed the wavefront's LDS");
+    static_assert(S::kSpan * sizeof(io_t) <= kGroupSlice * sizeof(float), "2-D span exceeds the wavefront's LDS");
     const S st(static_cast<const io_t*>(gd.A), static_cast<const io_t*>(gd.B), L, g);
-    for (int64_t base = it.first_tile; base < end; base += kT)
-      staged2d_tiles<S, kT>(st, slice, X, Y, base, end, gd.count, threadIdx.x & 63);
+    for (int64_t base = it.first_tile; base < end; base += S::kT)
+      staged2d_tiles<S>(st, slice, X, Y, base, end, gd.count, threadIdx.x & 63);
   } else {
+    constexpr int kT = 4;
     using T = Tile2D<M, N, kVec, false>;
     const T tile(static_cast<const io_t*>(gd.A), static_cast<const io_t*>(gd.B), L, g);
     for (int64_t base = it.first_tile; base < end; base += kT) {

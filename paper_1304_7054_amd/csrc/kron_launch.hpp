@@ -83,7 +83,8 @@ int launch2d_n(const typename M::io_t* A, const typename M::io_t* B, const typen
   if constexpr (kStageable<M, N, 2>) {
     if (sh.variant == 3) {
       auto k = kron2d_staged_kernel<M, N, kTrans>;
-      const int64_t waves = (ntiles + 3) / 4;
+      constexpr int kT = Staged2D<M, N, kTrans>::kT;
+      const int64_t waves = (ntiles + kT - 1) / kT;
       hipLaunchKernelGGL(k, dim3(grid_blocks(waves, occupancy_blocks(k), sh.blocks_per_cu)), dim3(kBlock), 0,
                          stream, A, B, X, Y, batch, ntiles);
       return 0;

@@ -35,26 +35,29 @@ __device__ __forceinline__ io_t narrow(T v) {
   else return (io_t)v;
 }
 
+// Copies between global memory and an LDS slice move 16-byte vectors (any
+// element type) when both sides are 16-byte aligned, one vector per lane per
+// step, with an element-wise tail; otherwise element by element.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+template <typename io_t>
+__device__ __forceinline__ bool both_aligned16(const void* a, const void* b) {
+  return ((reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(b)) % 16) == 0;
+}
+
 // Copy `count` consecutive elements from global memory into an LDS slice.
 template <typename io_t>
 __device__ __forceinline__ void copy_in(const io_t* __restrict__ src, io_t* lds, int count, int lane) {
-  const bool vec = ((reinterpret_cast<uintptr_t>(src) % Mem<io_t>::kAlign) == 0) &&
-                   ((reinterpret_cast<uintptr_t>(lds) % 16) == 0) && (count % 4 == 0);
-  if (vec) {
-    for (int i = lane * 4; i < count; i += 256) {
-      if constexpr (sizeof(io_t) == 4) {
-        *reinterpret_cast<f32x4*>(lds + i) = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(src + i));
-      } else if constexpr (sizeof(io_t) == 8) {
-        typedef double f64x2 __attribute__((ext_vector_type(2)));
-        *reinterpret_cast<f64x2*>(lds + i) = __builtin_nontemporal_load(reinterpret_cast<const f64x2*>(src + i));
-        *reinterpret_cast<f64x2*>(lds + i + 2) = __builtin_nontemporal_load(reinterpret_cast<const f64x2*>(src + i + 2));
-      } else {
-        *reinterpret_cast<u16x4*>(lds + i) = __builtin_nontemporal_load(reinterpret_cast<const u16x4*>(src + i));
-      }
-    }
-  } else {
-    for (int i = lane; i < count; i += 64) lds[i] = __builtin_nontemporal_load(src + i);
+  constexpr int V = 16 / sizeof(io_t);
+  int done = 0;
+  if (both_aligned16<io_t>(src, lds)) {
+    const int nv = count / V;
+    const u32x4* s4 = reinterpret_cast<const u32x4*>(src);
+    u32x4* d4 = reinterpret_cast<u32x4*>(lds);
+    for (int i = lane; i < nv; i += 64) d4[i] = __builtin_nontemporal_load(s4 + i);
+    done = nv * V;
   }
+  for (int i = done + lane; i < count; i += 64) lds[i] = __builtin_nontemporal_load(src + i);
 }
 
 template <typename io_t>
@@ -62,25 +65,19 @@ __device__ __forceinline__ void zero_fill(io_t* lds, int from, int to, int lane)
   for (int i = from + lane; i < to; i += 64) lds[i] = io_t(0);
 }
 
+// Copy `count` consecutive elements from an LDS slice to global memory.
 template <typename io_t>
 __device__ __forceinline__ void copy_out(io_t* __restrict__ dst, const io_t* lds, int count, int lane) {
-  const bool vec = ((reinterpret_cast<uintptr_t>(dst) % Mem<io_t>::kAlign) == 0) &&
-                   ((reinterpret_cast<uintptr_t>(lds) % 16) == 0) && (count % 4 == 0);
-  if (vec) {
-    for (int i = lane * 4; i < count; i += 256) {
-      if constexpr (sizeof(io_t) == 4) {
-        __builtin_nontemporal_store(*reinterpret_cast<const f32x4*>(lds + i), reinterpret_cast<f32x4*>(dst + i));
-      } else if constexpr (sizeof(io_t) == 8) {
-        typedef double f64x2 __attribute__((ext_vector_type(2)));
-        __builtin_nontemporal_store(*reinterpret_cast<const f64x2*>(lds + i), reinterpret_cast<f64x2*>(dst + i));
-        __builtin_nontemporal_store(*reinterpret_cast<const f64x2*>(lds + i + 2), reinterpret_cast<f64x2*>(dst + i + 2));
-      } else {
-        __builtin_nontemporal_store(*reinterpret_cast<const u16x4*>(lds + i), reinterpret_cast<u16x4*>(dst + i));
-      }
-    }
-  } else {
-    for (int i = lane; i < count; i += 64) __builtin_nontemporal_store(lds[i], dst + i);
+  constexpr int V = 16 / sizeof(io_t);
+  int done = 0;
+  if (both_aligned16<io_t>(dst, lds)) {
+    const int nv = count / V;
+    const u32x4* s4 = reinterpret_cast<const u32x4*>(lds);
+    u32x4* d4 = reinterpret_cast<u32x4*>(dst);
+    for (int i = lane; i < nv; i += 64) __builtin_nontemporal_store(s4[i], d4 + i);
+    done = nv * V;
   }
+  for (int i = done + lane; i < count; i += 64) __builtin_nontemporal_store(lds[i], dst + i);
 }
 
 // Element offsets of a tile's slots (memory axes 0 slow, 1, 2 fast).
@@ -236,7 +233,12 @@ struct Staged2D {
   static constexpr int kOps = Q * Q;
   static constexpr int E = G::E;
   static constexpr int kElems = kOps * E;
-  static constexpr int kSlice = (kElems + 7) / 8 * 8;
+  // Consecutive tiles sit back to back in LDS as they do in memory, so that
+  // a group of kT tiles moves as one span; kT is sized for about 4 KB per
+  // wavefront and group (the copy size that keeps HBM busiest), 2..8 tiles.
+  static constexpr int kTileBytes = kElems * (int)sizeof(io_t);
+  static constexpr int kT = 4096 / kTileBytes < 2 ? 2 : 4096 / kTileBytes > 8 ? 8 : 4096 / kTileBytes;
+  static constexpr int kSpan = (kT * kElems + 7) / 8 * 8;
 
   Tile tile;
   LaneSlots<N, 2> in, out;
@@ -261,51 +263,63 @@ struct Staged2D {
   }
 };
 
-// kT consecutive tiles (from tile t0, at most `last` - t0 of them) through
-// kT LDS slices of S::kSlice elements each; a packed tile with a non-finite
-// result is redone per operand as in 3-D.
-template <class S, int kT>
-__device__ __forceinline__ void staged2d_tiles(const S& st, typename S::io_t* slices, const typename S::io_t* X,
+// kT consecutive tiles (from tile t0; those at or past `last` hold nothing)
+// through one LDS span: the run of operands they hold is copied in as one
+// piece, the tail of the span zero-filled, and the results copied out as one
+// piece.  A packed tile with a non-finite result is redone per operand as in
+// 3-D; its span part is then left out of the copy-out.
+template <class S>
+__device__ __forceinline__ void staged2d_tiles(const S& st, typename S::io_t* span, const typename S::io_t* X,
                                                typename S::io_t* Y, int64_t t0, int64_t last, int64_t batch,
                                                int l) {
   using io_t = typename S::io_t;
   using acc_t = typename S::acc_t;
-  int nops[kT];
-#pragma unroll
-  for (int j = 0; j < kT; ++j) {
-    const int64_t t = t0 + j;
-    const int64_t rem = t < last ? batch - t * S::kOps : 0;
-    nops[j] = (int)(rem < S::kOps ? rem : S::kOps);
-  }
+  constexpr int kT = S::kT;
+  const int64_t ops_left = batch - t0 * S::kOps;
+  const int64_t tiles_left = last - t0;
+  const int64_t cap = (tiles_left < kT ? tiles_left : kT) * S::kOps;
+  const int nops_all = (int)(ops_left < cap ? ops_left : cap);
+  const int count = nops_all * S::E;
+  const io_t* Xs = X + t0 * S::kElems;
+  io_t* Ys = Y + t0 * S::kElems;
   wave_sync_lds();
-#pragma unroll
-  for (int j = 0; j < kT; ++j) zero_fill(slices + j * S::kSlice, nops[j] * S::E, S::kElems, l);
-#pragma unroll
-  for (int j = 0; j < kT; ++j)
-    if (nops[j] > 0) copy_in(X + (t0 + j) * S::kElems, slices + j * S::kSlice, nops[j] * S::E, l);
+  zero_fill(span, count, kT * S::kElems, l);
+  copy_in(Xs, span, count, l);
   wave_sync_lds();
   acc_t v[kT];
 #pragma unroll
-  for (int j = 0; j < kT; ++j) v[j] = st.tile.compute(st.read(slices + j * S::kSlice));
+  for (int j = 0; j < kT; ++j) v[j] = st.tile.compute(st.read(span + j * S::kElems));
   bool bad[kT];
+  bool any_bad = false;
 #pragma unroll
-  for (int j = 0; j < kT; ++j) bad[j] = S::kOps > 1 && nops[j] > 0 && __any(!all_finite(v[j]));
+  for (int j = 0; j < kT; ++j) {
+    const int nops = nops_all - j * S::kOps;
+    bad[j] = S::kOps > 1 && nops > 0 && __any(!all_finite(v[j]));
+    any_bad |= bad[j];
+  }
   wave_sync_lds();
 #pragma unroll
   for (int j = 0; j < kT; ++j)
-    if (!bad[j]) st.write(slices + j * S::kSlice, v[j]);
+    if (!bad[j]) st.write(span + j * S::kElems, v[j]);
   wave_sync_lds();
-#pragma unroll
-  for (int j = 0; j < kT; ++j)
-    if (nops[j] > 0 && !bad[j]) copy_out(Y + (t0 + j) * S::kElems, slices + j * S::kSlice, nops[j] * S::E, l);
+  if (!any_bad) {
+    copy_out(Ys, span, count, l);
+    return;
+  }
   if constexpr (S::kOps > 1) {
     for (int j = 0; j < kT; ++j) {
-      if (!bad[j]) continue;
-      io_t* sl = slices + j * S::kSlice;
-      const io_t* Xt = X + (t0 + j) * S::kElems;
-      io_t* Yt = Y + (t0 + j) * S::kElems;
+      const int nops = nops_all - j * S::kOps;
+      if (nops <= 0) break;
+      const int nj = nops < S::kOps ? nops : S::kOps;
+      io_t* sl = span + j * S::kElems;
+      if (!bad[j]) {
+        copy_out(Ys + j * S::kElems, sl, nj * S::E, l);
+        continue;
+      }
+      const io_t* Xt = Xs + j * S::kElems;
+      io_t* Yt = Ys + j * S::kElems;
       // this tile's results were not written back: redo it operand by operand
-      for (int o = 0; o < nops[j]; ++o) {
+      for (int o = 0; o < nj; ++o) {
         wave_sync_lds();
         zero_fill(sl, 0, S::kElems, l);
         wave_sync_lds();
@@ -329,15 +343,15 @@ __global__ __launch_bounds__(kBlock) void kron2d_staged_kernel(const typename M:
                                                                int64_t ntiles) {
   using S = Staged2D<M, N, kTrans>;
   using io_t = typename M::io_t;
-  constexpr int kT = 4;
-  __shared__ __attribute__((aligned(16))) io_t slices[kBlock / kWave][kT * S::kSlice];
+  constexpr int kT = S::kT;
+  __shared__ __attribute__((aligned(16))) io_t slices[kBlock / kWave][S::kSpan];
   const int l = threadIdx.x & 63, L = l & 15, g = l >> 4;
   io_t* mine = slices[threadIdx.x >> 6];
   const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * kBlock) >> 6;
   const S st(A, B, L, g);
   for (int64_t base = wave * kT; base < ntiles; base += nwaves * kT)
-    staged2d_tiles<S, kT>(st, mine, X, Y, base, ntiles, batch, l);
+    staged2d_tiles<S>(st, mine, X, Y, base, ntiles, batch, l);
 }
 
 }  // namespace kron
