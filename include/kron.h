@@ -198,8 +198,9 @@ int kron3d_backward_f64(int n, const double* A, const double* B, const double* C
           register exchange); 3 = 1 + 2; 4/5 = contiguous rows with a window
           of 2/4 slab loads in flight; 6/7 = 4/5 with the next tile's first
           slabs requested early; 8 = tiles staged through LDS (n != 16, FP32,
-          bf16x3 and bf16 storage).  A variant a size cannot use falls back
-          to 0.  The paper
+          bf16x3 and bf16 storage; otherwise variant 0); 9/10 = n = 16,
+          contiguous rows, the result stores interleaved with the next
+          tile's slab loads (window 2/4; otherwise variant 4).  The paper
    picks its kernel method by matrix size and fixes the number of thread
    blocks (Sections 4 and 5); here the choice is a per-(mode, dim, n) table
    that an autotuner can fill.  Process-wide, not thread-safe against

@@ -52,10 +52,10 @@ LaunchShape default_shape(int mode, int dim, int n) {
   }
   if (dim == 3) {
     switch (mode) {
-      case 0: return LaunchShape{0, 4};  // FP32: contiguous rows, 2-slab window
-      case 1: return LaunchShape{2, 7};  // FP64: 4-slab window + next tile, 2 workgroups per CU
-      case 2: return LaunchShape{2, 6};  // bf16x3: 2-slab window + next tile, 2 workgroups per CU
-      default: return LaunchShape{0, 5}; // bf16 storage: 4-slab window
+      case 0: return LaunchShape{0, 9};   // FP32: stores interleaved with the next tile, 2-slab window
+      case 1: return LaunchShape{2, 9};   // FP64: the same, 2 workgroups per CU
+      case 2: return LaunchShape{0, 10};  // bf16x3: stores interleaved, 4-slab window
+      default: return LaunchShape{0, 5};  // bf16 storage: contiguous rows, 4-slab window
     }
   }
   return LaunchShape{0, 0};
@@ -76,7 +76,7 @@ int set_launch_shape(int mode, int dim, int n, int blocks_per_cu, int variant) {
   if (dim < 2 || dim > 3) return -2;
   if (n < 1 || n > 16) return -3;
   if (blocks_per_cu < -1 || blocks_per_cu > 64) return -4;
-  if (variant < 0 || variant > (dim == 3 ? 8 : 3)) return -5;
+  if (variant < 0 || variant > (dim == 3 ? 10 : 3)) return -5;
   g_shape[mode][dim - 2][n].store(blocks_per_cu < 0 ? -1 : blocks_per_cu * 16 + variant, std::memory_order_relaxed);
   return 0;
 }
@@ -411,11 +411,15 @@ int kron_autotune(int mode, int dim, int n, const void* A, const void* B, const 
     if (e0) (void)hipEventDestroy(e0);
     return (int)e;
   }
-  const int nvar = dim == 3 ? 9 : 4;
+  // candidate variants: 2-D 0-3; 3-D 0-7 plus 9-10 (n = 16) or 8 (other n)
+  int vars[11], nvar = 0;
+  for (int v = 0; v <= (dim == 3 ? 10 : 3); ++v)
+    if (dim == 2 || (v == 8 ? n != 16 : v < 8 || n == 16)) vars[nvar++] = v;
   const int blocks[] = {0, 1, 2, 3, 4};
   float best = 3.4e38f;
   int bb = 0, bv = 0, rc = 0;
-  for (int v = 0; v < nvar && rc == 0; ++v) {
+  for (int vi = 0; vi < nvar && rc == 0; ++vi) {
+    const int v = vars[vi];
     for (int b : blocks) {
       kron::set_launch_shape(mode, dim, n, b, v);
       if ((rc = run()) != 0) break;  // warm-up (code object load)

@@ -204,7 +204,7 @@ struct Grad3DStaged {
   static constexpr int kOps = Q * Q * Q;
   static constexpr int E = G::E;
   static constexpr int kElems = kOps * E;
-  static constexpr int kSlice = (kElems + 7) / 8 * 8;
+  static constexpr int kSlice = (kElems + kStagePad + 7) / 8 * 8;
   fac_t fA, fB, fC;
   int L, g;
 
@@ -269,17 +269,21 @@ __global__ __launch_bounds__(kGradBlock) void kron_grad_partial_kernel(
   if constexpr (Dim == 3 && kGradStaged<M, N>) {
     using GS = Grad3DStaged<M, N>;
     __shared__ __attribute__((aligned(16))) io_t slices[kGradBlock / kWave][2][GS::kSlice];
-    io_t* ldsX = slices[threadIdx.x >> 6][0];
-    io_t* ldsY = slices[threadIdx.x >> 6][1];
+    io_t* sliceX = slices[threadIdx.x >> 6][0];
+    io_t* sliceY = slices[threadIdx.x >> 6][1];
     const GS gr(A, B, C, L, g);
     for (int64_t t = wave; t < ntiles; t += nwaves) {
       const int64_t rem = batch - t * GS::kOps;
       const int count = (int)((rem < GS::kOps ? rem : GS::kOps) * GS::E);
+      const io_t* Xt = X + t * GS::kElems;
+      const io_t* dYt = dY + t * GS::kElems;
+      io_t* ldsX = stage_base(sliceX, Xt);
+      io_t* ldsY = stage_base(sliceY, dYt);
       wave_sync_lds();
       zero_fill(ldsX, count, GS::kElems, l);
       zero_fill(ldsY, count, GS::kElems, l);
-      copy_in(X + t * GS::kElems, ldsX, count, l);
-      copy_in(dY + t * GS::kElems, ldsY, count, l);
+      copy_in(Xt, ldsX, count, l);
+      copy_in(dYt, ldsY, count, l);
       wave_sync_lds();
       if (which & 1) gr.template tile<0>(ldsX, ldsY, acc[0]);
       if (which & 2) gr.template tile<1>(ldsX, ldsY, acc[1]);

@@ -484,4 +484,64 @@ __global__ __launch_bounds__(kBlock) void kron3d_kernel(const typename M::io_t* 
   }
 }
 
+// n = 16 (one operand per tile): the result of tile t is written one slab
+// at a time, and between two slab stores the wavefront runs stages 1-2 on a
+// slab of its next tile and requests the slab kWindow further on.  Reads and
+// writes then alternate per 1 KiB row instead of a whole tile of each in a
+// burst; contiguous-row stage order, so every access is one 1 KiB row.
+template <class M, bool kTrans, int kWindow>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void kron3d_stream_kernel(const typename M::io_t* __restrict__ A,
+                                                               const typename M::io_t* __restrict__ B,
+                                                               const typename M::io_t* __restrict__ C,
+                                                               const typename M::io_t* __restrict__ X,
+                                                               typename M::io_t* __restrict__ Y, int64_t ntiles) {
+  using T = Tile3D<M, 16, true, kTrans, true>;
+  using acc_t = typename M::acc_t;
+  static_assert(T::kOps == 1, "one operand per tile");
+  constexpr int64_t kStep = T::E;
+  const int l = threadIdx.x & 63, L = l & 15, g = l >> 4;
+  const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * kBlock) >> 6;
+  const T tile(A, B, C, L, g);
+  int64_t t = wave;
+  if (t >= ntiles) return;
+  acc_t v[16], nx[16];
+  {
+    const typename M::io_t* Xt = X + t * kStep;
+#pragma unroll
+    for (int b = 0; b < kWindow; ++b) tile.load_slab(Xt, 1, b, v[b]);
+#pragma unroll
+    for (int b = 0; b < 16; ++b) {
+      __builtin_amdgcn_sched_barrier(0);
+      tile.stage12(v[b]);
+      if (b + kWindow < 16) tile.load_slab(Xt, 1, b + kWindow, v[b + kWindow]);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    tile.stage3(v);
+  }
+  for (;;) {
+    typename M::io_t* Yt = Y + t * kStep;
+    const int64_t tn = t + nwaves;
+    if (tn >= ntiles) {
+      tile.store(Yt, 1, v);
+      return;
+    }
+    const typename M::io_t* Xn = X + tn * kStep;
+#pragma unroll
+    for (int b = 0; b < kWindow; ++b) tile.load_slab(Xn, 1, b, nx[b]);
+#pragma unroll
+    for (int b = 0; b < 16; ++b) {
+      __builtin_amdgcn_sched_barrier(0);
+      tile.store_slab(Yt, 1, b, v[b]);
+      tile.stage12(nx[b]);
+      if (b + kWindow < 16) tile.load_slab(Xn, 1, b + kWindow, nx[b + kWindow]);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    tile.stage3(nx);
+#pragma unroll
+    for (int b = 0; b < 16; ++b) v[b] = nx[b];
+    t = tn;
+  }
+}
+
 }  // namespace kron

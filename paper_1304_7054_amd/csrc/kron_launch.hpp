@@ -6,6 +6,8 @@
 
 #include <atomic>
 #include <cstdint>
+#include <mutex>
+#include <unordered_map>
 
 #include "kron_kernels.hpp"
 #include "kron_staged.hpp"
@@ -13,21 +15,23 @@
 
 namespace kron {
 
-// Resident workgroups per CU for a kernel, queried once per instantiation.
+// Resident workgroups per CU for a kernel, queried once per kernel (keyed by
+// its address: kernels of one signature must not share the value).
+inline int occupancy_blocks_of(const void* kernel) {
+  static std::mutex mu;
+  static std::unordered_map<const void*, int> cache;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = cache.find(kernel);
+  if (it != cache.end()) return it->second;
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, kBlock, 0) != hipSuccess || nb < 1) nb = 1;
+  cache.emplace(kernel, nb);
+  return nb;
+}
+
 template <typename K>
 int occupancy_blocks(K kernel) {
-  static std::atomic<int> cached{0};
-  int v = cached.load(std::memory_order_relaxed);
-  if (v == 0) {
-    int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(kernel), kBlock, 0) !=
-            hipSuccess ||
-        nb < 1)
-      nb = 1;
-    cached.store(nb, std::memory_order_relaxed);
-    v = nb;
-  }
-  return v;
+  return occupancy_blocks_of(reinterpret_cast<const void*>(kernel));
 }
 
 // Workgroups to launch: enough to cover the work, at most `per_cu` (or the
@@ -135,6 +139,17 @@ void launch3d_v(int variant, const typename M::io_t* A, const typename M::io_t* 
     case 7:
       launch3d_k<M, N, kTrans, kVec, true, true, 4>(A, B, C, X, Y, batch, ntiles, per_cu, stream);
       break;
+    case 9:
+    case 10:
+      if constexpr (N == 16 && kVec) {
+        auto k = variant == 9 ? kron3d_stream_kernel<M, kTrans, 2> : kron3d_stream_kernel<M, kTrans, 4>;
+        hipLaunchKernelGGL(k, dim3(grid_blocks(ntiles, occupancy_blocks(k), per_cu)), dim3(kBlock), 0, stream, A, B,
+                           C, X, Y, ntiles);
+      } else {
+        // same stage order (contiguous rows), slab window 2
+        launch3d_k<M, N, kTrans, kVec, false, true, 2>(A, B, C, X, Y, batch, ntiles, per_cu, stream);
+      }
+      break;
     default:
       launch3d_k<M, N, kTrans, kVec, false, false, 0>(A, B, C, X, Y, batch, ntiles, per_cu, stream);
   }
@@ -145,7 +160,9 @@ void launch3d_v(int variant, const typename M::io_t* A, const typename M::io_t* 
 // 3 = 1 + 2, 4/5 contiguous rows with a window of 2/4 slab loads in flight,
 // 6/7 = 4/5 with the next tile's first slabs requested before stage 3,
 // 8 = tiles staged through LDS (n != 16, elements of at most 4 bytes; other
-// sizes fall back to variant 0).
+// sizes fall back to variant 0), 9/10 = n = 16 with the result stores
+// interleaved with the next tile's loads and stages 1-2, window 2/4 (other
+// sizes and unaligned arrays run variant 4, the same stage order).
 template <class M, int N, bool kTrans>
 int launch3d_n(const typename M::io_t* A, const typename M::io_t* B, const typename M::io_t* C,
                const typename M::io_t* X, typename M::io_t* Y, int64_t batch, hipStream_t stream, int mode) {

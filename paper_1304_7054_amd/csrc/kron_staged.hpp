@@ -35,29 +35,83 @@ __device__ __forceinline__ io_t narrow(T v) {
   else return (io_t)v;
 }
 
-// Copies between global memory and an LDS slice move 16-byte vectors (any
-// element type) when both sides are 16-byte aligned, one vector per lane per
-// step, with an element-wise tail; otherwise element by element.
+// Copies between global memory and an LDS slice.  A slice is placed at the
+// same offset modulo 16 bytes as the global run it receives (stage_base), so
+// both sides of the copy are vector-aligned for any tile size and start:
+// a scalar head, 16-byte vectors, a scalar tail.  Each lane issues a batch of
+// loads before it writes any of them to LDS, so a wavefront has several
+// requests in flight instead of one round trip per element group.  When the
+// two sides still differ modulo 16 bytes (an output array aligned unlike the
+// input), the copy goes element by element, also in batches.
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
+constexpr int kStagePad = 8;  // spare elements per slice for the alignment shift
+
 template <typename io_t>
-__device__ __forceinline__ bool both_aligned16(const void* a, const void* b) {
-  return ((reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(b)) % 16) == 0;
+__device__ __forceinline__ io_t* stage_base(io_t* lds, const io_t* src) {
+  return lds + (int)((reinterpret_cast<uintptr_t>(src) & 15) / sizeof(io_t));
+}
+
+template <typename T, int kB>
+__device__ __forceinline__ void batched_in(const T* __restrict__ src, T* lds, int n, int lane) {
+  for (int b = 0; b < n; b += 64 * kB) {
+    T r[kB];
+#pragma unroll
+    for (int k = 0; k < kB; ++k) {
+      const int i = b + 64 * k + lane;
+      if (i < n) r[k] = __builtin_nontemporal_load(src + i);
+    }
+#pragma unroll
+    for (int k = 0; k < kB; ++k) {
+      const int i = b + 64 * k + lane;
+      if (i < n) lds[i] = r[k];
+    }
+  }
+}
+
+template <typename T, int kB>
+__device__ __forceinline__ void batched_out(T* __restrict__ dst, const T* lds, int n, int lane) {
+  for (int b = 0; b < n; b += 64 * kB) {
+    T r[kB];
+#pragma unroll
+    for (int k = 0; k < kB; ++k) {
+      const int i = b + 64 * k + lane;
+      if (i < n) r[k] = lds[i];
+    }
+#pragma unroll
+    for (int k = 0; k < kB; ++k) {
+      const int i = b + 64 * k + lane;
+      if (i < n) __builtin_nontemporal_store(r[k], dst + i);
+    }
+  }
+}
+
+// elements before `p` reaches a 16-byte boundary (at most count)
+template <typename io_t>
+__device__ __forceinline__ int head_elems(const io_t* p, int count) {
+  const int h = (int)(((16 - (reinterpret_cast<uintptr_t>(p) & 15)) & 15) / sizeof(io_t));
+  return h < count ? h : count;
+}
+
+template <typename io_t>
+__device__ __forceinline__ bool same_phase16(const void* a, const void* b) {
+  return ((reinterpret_cast<uintptr_t>(a) ^ reinterpret_cast<uintptr_t>(b)) & 15) == 0;
 }
 
 // Copy `count` consecutive elements from global memory into an LDS slice.
 template <typename io_t>
 __device__ __forceinline__ void copy_in(const io_t* __restrict__ src, io_t* lds, int count, int lane) {
   constexpr int V = 16 / sizeof(io_t);
-  int done = 0;
-  if (both_aligned16<io_t>(src, lds)) {
-    const int nv = count / V;
-    const u32x4* s4 = reinterpret_cast<const u32x4*>(src);
-    u32x4* d4 = reinterpret_cast<u32x4*>(lds);
-    for (int i = lane; i < nv; i += 64) d4[i] = __builtin_nontemporal_load(s4 + i);
-    done = nv * V;
+  if (!same_phase16<io_t>(src, lds)) {
+    batched_in<io_t, 16>(src, lds, count, lane);
+    return;
   }
-  for (int i = done + lane; i < count; i += 64) lds[i] = __builtin_nontemporal_load(src + i);
+  const int head = head_elems(src, count);
+  if (lane < head) lds[lane] = __builtin_nontemporal_load(src + lane);
+  const int nv = (count - head) / V;
+  batched_in<u32x4, 8>(reinterpret_cast<const u32x4*>(src + head), reinterpret_cast<u32x4*>(lds + head), nv, lane);
+  const int done = head + nv * V;
+  if (lane < count - done) lds[done + lane] = __builtin_nontemporal_load(src + done + lane);
 }
 
 template <typename io_t>
@@ -69,15 +123,16 @@ __device__ __forceinline__ void zero_fill(io_t* lds, int from, int to, int lane)
 template <typename io_t>
 __device__ __forceinline__ void copy_out(io_t* __restrict__ dst, const io_t* lds, int count, int lane) {
   constexpr int V = 16 / sizeof(io_t);
-  int done = 0;
-  if (both_aligned16<io_t>(dst, lds)) {
-    const int nv = count / V;
-    const u32x4* s4 = reinterpret_cast<const u32x4*>(lds);
-    u32x4* d4 = reinterpret_cast<u32x4*>(dst);
-    for (int i = lane; i < nv; i += 64) __builtin_nontemporal_store(s4[i], d4 + i);
-    done = nv * V;
+  if (!same_phase16<io_t>(dst, lds)) {
+    batched_out<io_t, 16>(dst, lds, count, lane);
+    return;
   }
-  for (int i = done + lane; i < count; i += 64) __builtin_nontemporal_store(lds[i], dst + i);
+  const int head = head_elems(dst, count);
+  if (lane < head) __builtin_nontemporal_store(lds[lane], dst + lane);
+  const int nv = (count - head) / V;
+  batched_out<u32x4, 8>(reinterpret_cast<u32x4*>(dst + head), reinterpret_cast<const u32x4*>(lds + head), nv, lane);
+  const int done = head + nv * V;
+  if (lane < count - done) __builtin_nontemporal_store(lds[done + lane], dst + done + lane);
 }
 
 // Element offsets of a tile's slots (memory axes 0 slow, 1, 2 fast).
@@ -125,7 +180,7 @@ struct Staged3D {
   static constexpr int kOps = Q * Q * Q;
   static constexpr int E = G::E;
   static constexpr int kElems = kOps * E;
-  static constexpr int kSlice = (kElems + 7) / 8 * 8;
+  static constexpr int kSlice = (kElems + kStagePad + 7) / 8 * 8;
 
   Tile tile;
   LaneSlots<N, 3> ls;
@@ -154,15 +209,16 @@ struct Staged3D {
   }
 };
 
-// One tile through an LDS slice of at least S::kSlice elements.  Packed
+// One tile through an LDS slice of S::kSlice elements (16-byte aligned).  Packed
 // tiles (several operands) whose result holds a non-finite value are redone
 // one operand at a time: the slice is zeroed, only operand o is copied in (at
 // its own place), the same code runs, and only operand o is copied out, so
 // IEEE propagation stays inside operand o.
 template <class S>
-__device__ __forceinline__ void staged3d_tile(const S& st, typename S::io_t* lds, const typename S::io_t* Xt,
+__device__ __forceinline__ void staged3d_tile(const S& st, typename S::io_t* slice, const typename S::io_t* Xt,
                                               typename S::io_t* Yt, int64_t rem, int l) {
   using acc_t = typename S::acc_t;
+  typename S::io_t* lds = stage_base(slice, Xt);
   const int nops = (int)(rem < S::kOps ? rem : S::kOps);
   for (int o = -1;;) {
     // o < 0: the whole tile; o >= 0: operand o alone
@@ -238,7 +294,7 @@ struct Staged2D {
   // wavefront and group (the copy size that keeps HBM busiest), 2..8 tiles.
   static constexpr int kTileBytes = kElems * (int)sizeof(io_t);
   static constexpr int kT = 4096 / kTileBytes < 2 ? 2 : 4096 / kTileBytes > 8 ? 8 : 4096 / kTileBytes;
-  static constexpr int kSpan = (kT * kElems + 7) / 8 * 8;
+  static constexpr int kSpan = (kT * kElems + kStagePad + 7) / 8 * 8;
 
   Tile tile;
   LaneSlots<N, 2> in, out;
@@ -282,6 +338,7 @@ __device__ __forceinline__ void staged2d_tiles(const S& st, typename S::io_t* sp
   const int count = nops_all * S::E;
   const io_t* Xs = X + t0 * S::kElems;
   io_t* Ys = Y + t0 * S::kElems;
+  span = stage_base(span, Xs);
   wave_sync_lds();
   zero_fill(span, count, kT * S::kElems, l);
   copy_in(Xs, span, count, l);

@@ -164,14 +164,17 @@ def test_nan_stays_in_its_operand(mode, dim, n):
 @pytest.mark.parametrize("n", [3, 16])
 @pytest.mark.parametrize("dim", [2, 3])
 def test_unaligned_pointers(dim, n):
-    """Operand arrays starting one element past an aligned address take the
-    element-wise path and give the same result."""
+    """Operand arrays that do not start on a 16-byte boundary (X and Y
+    offset alike or differently) take the element-wise or shifted-staging
+    paths and give the same bits."""
     _need_gpu()
     batch = gu.tiles_batch(dim, n)
     mats, X = _inputs(dim, n, batch, 77, "f32")
     a = gu.run("f32", dim, n, mats, X, batch)
     b = gu.run("f32", dim, n, mats, X, batch, x_offset=1, y_offset=3)
     assert np.array_equal(a, b)
+    c = gu.run("f32", dim, n, mats, X, batch, x_offset=2, y_offset=2)   # same phase, not 16-byte aligned
+    assert np.array_equal(a, c)
 
 
 @pytest.mark.parametrize("dim", [2, 3])
@@ -227,14 +230,18 @@ def test_launch_variants_agree(mode, dim, n):
     want = _oracle(dim, n, gu.rounded_inputs(mode, mats), gu.rounded_inputs(mode, [X])[0], batch)
     refs = {}
     try:
-        for variant in ([0, 1, 2, 3, 4, 5, 6, 7, 8] if dim == 3 else [0, 1, 2, 3]):
-            # 3-D variants 2..7 and 8 (LDS-staged) contract C, B, A; 0 and 1
-            # contract C, A, B.  A variant a size cannot use runs variant 0.
+        for variant in (list(range(11)) if dim == 3 else [0, 1, 2, 3]):
+            # 3-D variants 2..7, 8 (LDS-staged) and 9/10 (stores interleaved
+            # with the next tile, n = 16; variant 4 otherwise) contract C, B,
+            # A; 0 and 1 contract C, A, B.  Variant 8 at a size it cannot
+            # use runs variant 0.
             stageable = n != 16 and mode != "f64"
             if dim == 2:
                 order = 0
             elif variant == 8:
                 order = 1 if stageable else 0
+            elif variant >= 9:
+                order = 1
             else:
                 order = 1 if variant >= 2 else 0
             for blocks in (0, 1):
