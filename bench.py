@@ -28,7 +28,7 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, vendor figure
 PAPER_K20C = {("f32", 3, 16): 268, ("f32", 2, 16): 285, ("f32", 3, 10): 126, ("f32", 2, 10): 143,
               ("f64", 3, 16): 169, ("f64", 2, 16): 152, ("f64", 3, 10): 103, ("f64", 2, 10): 108}
 KERNEL_SOURCES = ["paper_1304_7054_amd/csrc/kron_tile.hpp", "paper_1304_7054_amd/csrc/kron_kernels.hpp",
-                  "paper_1304_7054_amd/csrc/kron_launch.hpp"]
+                  "paper_1304_7054_amd/csrc/kron_launch.hpp", "paper_1304_7054_amd/csrc/kron_abi.hip"]
 
 
 def parse():
@@ -36,6 +36,8 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=50)
     p.add_argument("--warmup", type=int, default=5)
+    p.add_argument("--device-warm", type=float, default=0.5,
+                   help="seconds of untimed launches before each measurement's warm-up steps (steady clocks)")
     p.add_argument("--only-headline", action="store_true", help="skip the other modes")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--summarize-profiles", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
@@ -84,11 +86,20 @@ def fn_for(mode, dim):
     }[(mode, dim)]
 
 
+DEVICE_WARM_S = 0.5
+
+
 def time_launches(torch, fn, args, steps, warmup):
     """Run `steps` launches bracketed by synchronisation; HIP events around
     every launch on the stream it is issued on.  Returns (wall ms/step,
     mean kernel ms, min kernel ms)."""
     stream = torch.cuda.current_stream()
+    # bring the device to its steady clocks first (untimed), then the W warm-up steps
+    t_end = time.perf_counter() + DEVICE_WARM_S
+    while time.perf_counter() < t_end:
+        for _ in range(20):
+            fn(*args, stream=stream)
+        torch.cuda.synchronize()
     for _ in range(warmup):
         fn(*args, stream=stream)
     torch.cuda.synchronize()
@@ -250,8 +261,22 @@ def traffic_record(khash):
     return rec.get("bytes_per_dispatch")
 
 
-HEADLINE_KERNEL = "kron::kron3d_kernel<kron::ModeF32, 16,"
+# the FP32 n = 16 3-D kernels (which one runs depends on the launch variant)
+HEADLINE_KERNELS = ("kron::kron3d_stream_kernel<kron::ModeF32,", "kron::kron3d_kernel<kron::ModeF32, 16,")
 CALIBRATION_KERNEL = "__amd_rocclr_copyBuffer"
+
+
+def headline_kernel_name():
+    """The kernel the FP32 3-D n = 16 launch runs under the current launch table."""
+    import paper_1304_7054_amd as kron
+    _, v = kron.kron_get_launch(kron.MODE_F32, 3, 16)
+    if v in (9, 10):
+        return f"kron3d_stream_kernel<ModeF32, window {2 if v == 9 else 4}> (variant {v})"
+    return f"kron3d_kernel<ModeF32, 16> (variant {v})"
+
+
+def _is_headline(name):
+    return any(k in name for k in HEADLINE_KERNELS)
 
 
 def _csv(dirname, suffix):
@@ -271,7 +296,7 @@ def summarize_profiles(trace_dir, fetch_dir, write_dir):
     for the plain 1 GiB device copy the --copy-calibration option issues
     (1 GiB read, 1 GiB written)."""
     stats = _csv(trace_dir, "kernel_stats.csv")
-    head = [r for r in stats if HEADLINE_KERNEL in r["Name"]]
+    head = sorted((r for r in stats if _is_headline(r["Name"])), key=lambda r: -int(r["Calls"]))
     if not head:
         raise RuntimeError("headline kernel not in the trace")
     h = head[0]
@@ -280,7 +305,7 @@ def summarize_profiles(trace_dir, fetch_dir, write_dir):
     one_gib_kib = float(1 << 20)
     for tag, d, counter in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
         rows = [r for r in _csv(d, "counter_collection.csv") if r["Counter_Name"] == counter]
-        kern = [float(r["Counter_Value"]) for r in rows if HEADLINE_KERNEL in r["Kernel_Name"]]
+        kern = [float(r["Counter_Value"]) for r in rows if r["Kernel_Name"] == h["Name"]]
         cal = [float(r["Counter_Value"]) for r in rows if r["Kernel_Name"] == CALIBRATION_KERNEL]
         # the calibration copies are the copyBuffer dispatches of 1 GiB: the largest ones
         cal = sorted(cal)[-3:]
@@ -295,18 +320,82 @@ def summarize_profiles(trace_dir, fetch_dir, write_dir):
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
     with open(os.path.join(ROOT, "profiles", "kron3d_f32_n16_traffic.json"), "w") as f:
         json.dump(out, f, indent=1)
+    with open(os.path.join(ROOT, "profiles", "kron3d_f32_n16.md"), "w") as f:
+        f.write(_profile_markdown(out, stats))
     print(json.dumps(out, indent=1))
     return out
 
 
+PROFILE_COMMANDS = """\
+export TMPDIR=/tmp
+rocprofv3 --kernel-trace --stats -d gpurun_out/prof_trace -o trace --output-format csv -- python bench.py --only-headline --no-cpu --copy-calibration --steps 20 --warmup 3
+rocprofv3 --pmc FETCH_SIZE -d gpurun_out/prof_fetch -o fetch --output-format csv -- python bench.py --only-headline --no-cpu --copy-calibration --device-warm 0 --steps 3 --warmup 1
+rocprofv3 --pmc WRITE_SIZE -d gpurun_out/prof_write -o write --output-format csv -- python bench.py --only-headline --no-cpu --copy-calibration --device-warm 0 --steps 3 --warmup 1
+python bench.py --summarize-profiles gpurun_out/prof_trace gpurun_out/prof_fetch gpurun_out/prof_write
+"""
+
+
+def _profile_markdown(out, stats):
+    rows = sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:5]
+    lines = [
+        "# Headline kernel: 3-D Kronecker action, FP32, n = 16, 65,536 arrays (1 GiB X + 1 GiB Y)",
+        "",
+        f"Kernel: `{out['kernel']}`",
+        "",
+        "## Commands (repository root, on the MI355X)",
+        "",
+        "```",
+        PROFILE_COMMANDS.rstrip(),
+        "```",
+        "",
+        "## Kernel trace (`--stats`), top kernels of the traced run",
+        "",
+        "| kernel | calls | avg us | min us | max us | % |",
+        "|---|---|---|---|---|---|",
+    ]
+    for r in rows:
+        lines.append(f"| `{r['Name'][:90]}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                     f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.1f} |")
+    lines += [
+        "",
+        f"The headline kernel's {out['calls']} calls include the untimed device warm-up launches (0.5 s), "
+        "3 warm-up steps and 20 timed steps; bench.py's own HIP-event average in the same run is the "
+        "`kernel_ms` of its JSON line.",
+        "",
+        "## HBM traffic per dispatch (`--pmc`, one counter per run)",
+        "",
+        "FETCH_SIZE and WRITE_SIZE are KiB per dispatch.  The calibration kernel is the plain 1 GiB "
+        "device-to-device copy (`__amd_rocclr_copyBuffer`, issued by `--copy-calibration`: 1 GiB read, "
+        "1 GiB written); each counter is scaled by (1 GiB / its reading for that copy).",
+        "",
+        "| counter | headline kernel (raw KiB) | 1 GiB copy (raw KiB) | scale | headline bytes |",
+        "|---|---|---|---|---|",
+        f"| FETCH_SIZE | {out['fetch_kib_raw']:.0f} | {out['fetch_calibration_kib_raw']:.0f} | "
+        f"{out['fetch_scale']:.4f} | {out['fetch_bytes']:.0f} |",
+        f"| WRITE_SIZE | {out['write_kib_raw']:.0f} | {out['write_calibration_kib_raw']:.0f} | "
+        f"{out['write_scale']:.4f} | {out['write_bytes']:.0f} |",
+        "",
+        f"Total {out['bytes_per_dispatch']:.0f} bytes per dispatch vs {out['alg_bytes_per_dispatch']} "
+        f"algorithmic (X read once, Y written once): ratio "
+        f"{out['bytes_per_dispatch'] / out['alg_bytes_per_dispatch']:.5f}.",
+        "",
+        f"Kernel sources hash (bench.py `kernel_hash`): `{out['kernel_hash']}`; bench.py reports "
+        "`roofline.traffic` only while the sources hash to this value.",
+        "",
+    ]
+    return "\n".join(lines)
+
+
 def main():
     args = parse()
+    global DEVICE_WARM_S
+    DEVICE_WARM_S = max(0.0, args.device_warm)
     if args.summarize_profiles:
         summarize_profiles(*args.summarize_profiles)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the batch splits into independent per-GPU shards; see DESIGN.md)", file=sys.stderr)
+              "(the batch splits into independent per-GPU shards with no communication)", file=sys.stderr)
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():
@@ -346,7 +435,7 @@ def main():
     khash = kernel_hash()
     roof = {"bound": "hbm", "achieved": head["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(head["gbs"] / HBM_PEAK_GBS, 4), "traffic": traffic_record(khash),
-            "kernel": "kron3d_kernel<ModeF32, 16>", "alg_bytes_per_launch": head["alg_bytes"],
+            "kernel": headline_kernel_name(), "alg_bytes_per_launch": head["alg_bytes"],
             "kernel_ms": head["ms"]}
     line = {
         "metric": "Kron-action GFLOP/s + % HBM roofline, 3-D n=16 FP32: plain vs bf16x3 MFMA",

@@ -53,7 +53,7 @@ LaunchShape default_shape(int mode, int dim, int n) {
   if (dim == 3) {
     switch (mode) {
       case 0: return LaunchShape{0, 9};   // FP32: stores interleaved with the next tile, 2-slab window
-      case 1: return LaunchShape{2, 9};   // FP64: the same, 2 workgroups per CU
+      case 1: return LaunchShape{2, 7};   // FP64: 4-slab window + next tile, 2 workgroups per CU
       case 2: return LaunchShape{0, 10};  // bf16x3: stores interleaved, 4-slab window
       default: return LaunchShape{0, 5};  // bf16 storage: contiguous rows, 4-slab window
     }

@@ -489,8 +489,15 @@ __global__ __launch_bounds__(kBlock) void kron3d_kernel(const typename M::io_t* 
 // slab of its next tile and requests the slab kWindow further on.  Reads and
 // writes then alternate per 1 KiB row instead of a whole tile of each in a
 // burst; contiguous-row stage order, so every access is one 1 KiB row.
+// Two 16-slab tiles live at once: with 4-byte elements they fit three
+// wavefronts per SIMD without spilling when the compiler is held to that.
+template <class M>
+constexpr int stream_waves() {
+  return sizeof(typename M::io_t) == 8 ? 1 : 3;
+}
+
 template <class M, bool kTrans, int kWindow>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void kron3d_stream_kernel(const typename M::io_t* __restrict__ A,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(stream_waves<M>()))) void kron3d_stream_kernel(const typename M::io_t* __restrict__ A,
                                                                const typename M::io_t* __restrict__ B,
                                                                const typename M::io_t* __restrict__ C,
                                                                const typename M::io_t* __restrict__ X,
