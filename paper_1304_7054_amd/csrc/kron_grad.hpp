@@ -82,7 +82,7 @@ struct GradLoader {
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const bool ok = vS && vL && vG[s] && (opL + opS + opG[s] < rem);
-      v[s] = ok ? P[offL + offS + offG[s]] : 0;
+      v[s] = ok ? in_global(P)[offL + offS + offG[s]] : 0;
     }
     return v;
   }
@@ -222,7 +222,7 @@ struct Grad3DStaged {
     if (!ps.valid) return v;
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-      const float x = lds[ls.base[s] + ps.off];
+      const float x = in_lds(lds)[ls.base[s] + ps.off];
       v[s] = ls.ok[s] ? x : 0.f;
     }
     return v;

@@ -34,10 +34,10 @@ template <>
 struct Mem<float> {
   using acc = f32x4;
   static constexpr int kAlign = 16;
-  __device__ static f32x4 load4(const float* p) { return __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(p)); }
-  __device__ static void store4(float* p, const f32x4& v) { __builtin_nontemporal_store(v, reinterpret_cast<f32x4*>(p)); }
-  __device__ static float load1(const float* p) { return __builtin_nontemporal_load(p); }
-  __device__ static void store1(float* p, float v) { __builtin_nontemporal_store(v, p); }
+  __device__ static f32x4 load4(const float* p) { return __builtin_nontemporal_load(in_global(reinterpret_cast<const f32x4*>(p))); }
+  __device__ static void store4(float* p, const f32x4& v) { __builtin_nontemporal_store(v, in_global(reinterpret_cast<f32x4*>(p))); }
+  __device__ static float load1(const float* p) { return __builtin_nontemporal_load(in_global(p)); }
+  __device__ static void store1(float* p, float v) { __builtin_nontemporal_store(v, in_global(p)); }
 };
 
 template <>
@@ -46,16 +46,16 @@ struct Mem<double> {
   typedef double f64x2 __attribute__((ext_vector_type(2)));
   static constexpr int kAlign = 16;
   __device__ static f64x4 load4(const double* p) {
-    f64x2 a = __builtin_nontemporal_load(reinterpret_cast<const f64x2*>(p));
-    f64x2 b = __builtin_nontemporal_load(reinterpret_cast<const f64x2*>(p + 2));
+    f64x2 a = __builtin_nontemporal_load(in_global(reinterpret_cast<const f64x2*>(p)));
+    f64x2 b = __builtin_nontemporal_load(in_global(reinterpret_cast<const f64x2*>(p + 2)));
     return f64x4{a[0], a[1], b[0], b[1]};
   }
   __device__ static void store4(double* p, const f64x4& v) {
-    __builtin_nontemporal_store(f64x2{v[0], v[1]}, reinterpret_cast<f64x2*>(p));
-    __builtin_nontemporal_store(f64x2{v[2], v[3]}, reinterpret_cast<f64x2*>(p + 2));
+    __builtin_nontemporal_store(f64x2{v[0], v[1]}, in_global(reinterpret_cast<f64x2*>(p)));
+    __builtin_nontemporal_store(f64x2{v[2], v[3]}, in_global(reinterpret_cast<f64x2*>(p + 2)));
   }
-  __device__ static double load1(const double* p) { return __builtin_nontemporal_load(p); }
-  __device__ static void store1(double* p, double v) { __builtin_nontemporal_store(v, p); }
+  __device__ static double load1(const double* p) { return __builtin_nontemporal_load(in_global(p)); }
+  __device__ static void store1(double* p, double v) { __builtin_nontemporal_store(v, in_global(p)); }
 };
 
 // bf16 storage: values are widened to FP32 on load and rounded to nearest even on store
@@ -64,17 +64,17 @@ struct Mem<uint16_t> {
   using acc = f32x4;
   static constexpr int kAlign = 8;
   __device__ static f32x4 load4(const uint16_t* p) {
-    u16x4 b = __builtin_nontemporal_load(reinterpret_cast<const u16x4*>(p));
+    u16x4 b = __builtin_nontemporal_load(in_global(reinterpret_cast<const u16x4*>(p)));
     return f32x4{from_bf16(bits_to_bf16(b[0])), from_bf16(bits_to_bf16(b[1])), from_bf16(bits_to_bf16(b[2])),
                  from_bf16(bits_to_bf16(b[3]))};
   }
   __device__ static void store4(uint16_t* p, const f32x4& v) {
     u16x4 b = {bf16_to_bits(to_bf16(v[0])), bf16_to_bits(to_bf16(v[1])), bf16_to_bits(to_bf16(v[2])),
                bf16_to_bits(to_bf16(v[3]))};
-    __builtin_nontemporal_store(b, reinterpret_cast<u16x4*>(p));
+    __builtin_nontemporal_store(b, in_global(reinterpret_cast<u16x4*>(p)));
   }
-  __device__ static float load1(const uint16_t* p) { return from_bf16(bits_to_bf16(__builtin_nontemporal_load(p))); }
-  __device__ static void store1(uint16_t* p, float v) { __builtin_nontemporal_store(bf16_to_bits(to_bf16(v)), p); }
+  __device__ static float load1(const uint16_t* p) { return from_bf16(bits_to_bf16(__builtin_nontemporal_load(in_global(p)))); }
+  __device__ static void store1(uint16_t* p, float v) { __builtin_nontemporal_store(bf16_to_bits(to_bf16(v)), in_global(p)); }
 };
 
 template <typename V>
@@ -108,7 +108,11 @@ struct Tile2D {
   static constexpr int Q = Geo<N>::Q;
   static constexpr int kOps = Q * Q;  // operands per tile
   static constexpr int E = N * N;     // elements per operand
-  static constexpr bool kStoreVec = kVec && (M::drow(0, 1) == 1);
+  // FP64 accumulators hold rows g + 4r; with vector I/O they are regrouped
+  // (rows 4g .. 4g + 3 per lane) before the store, so every lane writes 32
+  // contiguous bytes instead of four scattered 8-byte values.
+  static constexpr bool kRegroup = kVec && M::drow(0, 1) != 1;
+  static constexpr bool kStoreVec = kVec;
 
   fac_t fB, fA;
   AxisPart<N, E> pL;            // slot L on the slow axis (load and store)
@@ -122,7 +126,7 @@ struct Tile2D {
     fA = M::template load_fac<N, kTrans>(A, L, g, 1);
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-      AxisPart<N, E> pi(4 * g + s, 1, 1), po(M::drow(g, s), 1, 1);
+      AxisPart<N, E> pi(4 * g + s, 1, 1), po(kRegroup ? 4 * g + s : M::drow(g, s), 1, 1);
       offI[s] = pi.off; opI[s] = pi.op; vI[s] = pi.valid;
       offO[s] = po.off; opO[s] = po.op; vO[s] = po.valid;
     }
@@ -157,7 +161,9 @@ struct Tile2D {
     return M::template da<kS>(fA, M::template da_in<kS>(fB, x));
   }
 
-  __device__ __forceinline__ void store(io_t* Yt, int64_t rem, const acc_t& y, int only = -1) const {
+  __device__ __forceinline__ void store(io_t* Yt, int64_t rem, const acc_t& y_in, int only = -1) const {
+    acc_t y = y_in;
+    if constexpr (kRegroup) transpose_groups_regs(y);
     if constexpr (N == 16 && kStoreVec) {
       Mem<io_t>::store4(Yt + pL.off + offO[0], y);
     } else if constexpr (kStoreVec) {

@@ -59,12 +59,12 @@ __device__ __forceinline__ void batched_in(const T* __restrict__ src, T* lds, in
 #pragma unroll
     for (int k = 0; k < kB; ++k) {
       const int i = b + 64 * k + lane;
-      if (i < n) r[k] = __builtin_nontemporal_load(src + i);
+      if (i < n) r[k] = __builtin_nontemporal_load(in_global(src) + i);
     }
 #pragma unroll
     for (int k = 0; k < kB; ++k) {
       const int i = b + 64 * k + lane;
-      if (i < n) lds[i] = r[k];
+      if (i < n) in_lds(lds)[i] = r[k];
     }
   }
 }
@@ -76,12 +76,12 @@ __device__ __forceinline__ void batched_out(T* __restrict__ dst, const T* lds, i
 #pragma unroll
     for (int k = 0; k < kB; ++k) {
       const int i = b + 64 * k + lane;
-      if (i < n) r[k] = lds[i];
+      if (i < n) r[k] = in_lds(lds)[i];
     }
 #pragma unroll
     for (int k = 0; k < kB; ++k) {
       const int i = b + 64 * k + lane;
-      if (i < n) __builtin_nontemporal_store(r[k], dst + i);
+      if (i < n) __builtin_nontemporal_store(r[k], in_global(dst) + i);
     }
   }
 }
@@ -107,16 +107,16 @@ __device__ __forceinline__ void copy_in(const io_t* __restrict__ src, io_t* lds,
     return;
   }
   const int head = head_elems(src, count);
-  if (lane < head) lds[lane] = __builtin_nontemporal_load(src + lane);
+  if (lane < head) in_lds(lds)[lane] = __builtin_nontemporal_load(in_global(src) + lane);
   const int nv = (count - head) / V;
   batched_in<u32x4, 8>(reinterpret_cast<const u32x4*>(src + head), reinterpret_cast<u32x4*>(lds + head), nv, lane);
   const int done = head + nv * V;
-  if (lane < count - done) lds[done + lane] = __builtin_nontemporal_load(src + done + lane);
+  if (lane < count - done) in_lds(lds)[done + lane] = __builtin_nontemporal_load(in_global(src) + done + lane);
 }
 
 template <typename io_t>
 __device__ __forceinline__ void zero_fill(io_t* lds, int from, int to, int lane) {
-  for (int i = from + lane; i < to; i += 64) lds[i] = io_t(0);
+  for (int i = from + lane; i < to; i += 64) in_lds(lds)[i] = io_t(0);
 }
 
 // Copy `count` consecutive elements from an LDS slice to global memory.
@@ -128,11 +128,11 @@ __device__ __forceinline__ void copy_out(io_t* __restrict__ dst, const io_t* lds
     return;
   }
   const int head = head_elems(dst, count);
-  if (lane < head) __builtin_nontemporal_store(lds[lane], dst + lane);
+  if (lane < head) __builtin_nontemporal_store(in_lds(lds)[lane], in_global(dst) + lane);
   const int nv = (count - head) / V;
   batched_out<u32x4, 8>(reinterpret_cast<u32x4*>(dst + head), reinterpret_cast<const u32x4*>(lds + head), nv, lane);
   const int done = head + nv * V;
-  if (lane < count - done) __builtin_nontemporal_store(lds[done + lane], dst + done + lane);
+  if (lane < count - done) __builtin_nontemporal_store(in_lds(lds)[done + lane], in_global(dst) + done + lane);
 }
 
 // Element offsets of a tile's slots (memory axes 0 slow, 1, 2 fast).
@@ -194,7 +194,7 @@ struct Staged3D {
     if (!ps.valid) return v;
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-      const auto x = widen(lds[ls.base[s] + ps.off]);
+      const auto x = widen(in_lds(lds)[ls.base[s] + ps.off]);
       v[s] = ls.ok[s] ? x : decltype(x)(0);
     }
     return v;
@@ -205,7 +205,7 @@ struct Staged3D {
     if (!ps.valid) return;
 #pragma unroll
     for (int s = 0; s < 4; ++s)
-      if (ls.ok[s]) lds[ls.base[s] + ps.off] = narrow<io_t>(v[s]);
+      if (ls.ok[s]) in_lds(lds)[ls.base[s] + ps.off] = narrow<io_t>(v[s]);
   }
 };
 
@@ -306,7 +306,7 @@ struct Staged2D {
     acc_t v;
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-      const auto x = widen(lds[in.base[s]]);
+      const auto x = widen(in_lds(lds)[in.base[s]]);
       v[s] = in.ok[s] ? x : decltype(x)(0);
     }
     return v;
@@ -315,7 +315,7 @@ struct Staged2D {
   __device__ __forceinline__ void write(io_t* lds, const acc_t& v) const {
 #pragma unroll
     for (int r = 0; r < 4; ++r)
-      if (out.ok[r]) lds[out.base[r]] = narrow<io_t>(v[r]);
+      if (out.ok[r]) in_lds(lds)[out.base[r]] = narrow<io_t>(v[r]);
   }
 };
 

@@ -39,6 +39,24 @@ typedef uint16_t u16x4 __attribute__((ext_vector_type(4)));
 constexpr int kWave = 64;
 constexpr int kSlots = 16;
 
+// Address-space views.  HIP pointers are generic; where a pointer crosses an
+// out-of-line call the compiler can no longer tell global memory from LDS and
+// falls back to flat instructions, which count against both the memory and
+// the LDS wait counters (an LDS wait then also waits for every global load
+// in flight).  Every access below goes through one of these views instead.
+template <typename T>
+using global_ptr = __attribute__((address_space(1))) T*;
+template <typename T>
+using lds_ptr = __attribute__((address_space(3))) T*;
+template <typename T>
+__device__ __forceinline__ global_ptr<T> in_global(T* p) {
+  return (global_ptr<T>)p;
+}
+template <typename T>
+__device__ __forceinline__ lds_ptr<T> in_lds(T* p) {
+  return (lds_ptr<T>)p;
+}
+
 // ---- tile geometry ---------------------------------------------------------
 
 template <int N>
@@ -135,7 +153,7 @@ template <int N, bool kTrans, typename T>
 __device__ __forceinline__ T tile_entry(const T* M, int row, int col) {
   Slot<N> r(row), c(col);
   if (!(r.valid && c.valid) || r.sub != c.sub) return T(0);
-  return kTrans ? M[c.idx + N * r.idx] : M[r.idx + N * c.idx];
+  return kTrans ? in_global(M)[c.idx + N * r.idx] : in_global(M)[r.idx + N * c.idx];
 }
 
 // ---- precision modes -----------------------------------------------------------------
@@ -292,7 +310,7 @@ struct ModeBF16 {
       int col = kmap == 0 ? 4 * g + s : drow(g, s);
       Slot<N> r(L), c(col);
       uint16_t b = 0;
-      if (r.valid && c.valid && r.sub == c.sub) b = kTrans ? M[c.idx + N * r.idx] : M[r.idx + N * c.idx];
+      if (r.valid && c.valid && r.sub == c.sub) b = kTrans ? in_global(M)[c.idx + N * r.idx] : in_global(M)[r.idx + N * c.idx];
       f[s] = bits_to_bf16(b);
     }
     return f;
@@ -355,6 +373,23 @@ __device__ __forceinline__ void swap16(double& x, double& y) {
   auto hi = __builtin_amdgcn_permlane16_swap((uint32_t)(xb >> 32), (uint32_t)(yb >> 32), false, false);
   x = __builtin_bit_cast(double, ((uint64_t)hi[0] << 32) | lo[0]);
   y = __builtin_bit_cast(double, ((uint64_t)hi[1] << 32) | lo[1]);
+}
+
+// Within one accumulator: lane group g, register r -> lane group r,
+// register g (lane bit 5 trades with register bit 1, then lane bit 4 with
+// register bit 0).  For an FP64 accumulator (rows g + 4r) this leaves rows
+// 4g .. 4g + 3 in lane group g, i.e. four consecutive elements per lane.
+template <typename V>
+__device__ __forceinline__ void transpose_groups_regs(V& v) {
+  auto a = v[0], b = v[1], c = v[2], d = v[3];
+  swap32(a, c);
+  swap32(b, d);
+  swap16(a, b);
+  swap16(c, d);
+  v[0] = a;
+  v[1] = b;
+  v[2] = c;
+  v[3] = d;
 }
 
 template <typename V>

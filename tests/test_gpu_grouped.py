@@ -128,3 +128,64 @@ def test_mixed_workload_sampled():
             want = (oracle.kron2d if p.dim == 2 else oracle.kron3d)(p.n, *mats, p.X[q * e:(q + 1) * e], 1, "f64")
             got = Y[q * e:(q + 1) * e]
             assert np.linalg.norm(got - want) <= 1e-5 * np.linalg.norm(want), (p.dim, p.n, q)
+
+
+@pytest.mark.parametrize("dims", [(2,), (3,)])
+def test_grouped_one_phase_matches_single_group_kernels(dims):
+    """Plans with only 2-D or only 3-D groups (the other phase empty), an
+    unaligned group among them; every group's result equals, bit for bit,
+    the single-group FP32 entry point on the same arrays (same tile code and
+    stage order at the default launch shapes)."""
+    import paper_1304_7054_amd as kron
+    _need_gpu()
+    spec = [(d, n, c) for d in dims for n, c in ((3, 700), (7, 333), (10, 250), (16, 97))]
+    groups, host = _make_groups(spec, 21)
+    # one unaligned group: X and Y start one element into their buffers
+    g0 = groups[-1]
+    xs = torch.empty(g0["X"].numel() + 1, device=DEV)
+    xs[1:] = g0["X"]
+    ys = torch.full((g0["Y"].numel() + 1,), float("nan"), device=DEV)
+    g0["X"], g0["Y"] = xs[1:], ys[1:]
+    ws = torch.empty(kron.kron_grouped_workspace_size(groups), dtype=torch.uint8, device=DEV)
+    kron.kron_grouped_prepare(groups, ws)
+    kron.kron_grouped_launch(ws)
+    torch.cuda.synchronize()
+    _check(groups, host)
+    for g in groups:
+        ref = torch.full_like(g["Y"], float("nan"))
+        mats = [g[k] for k in "ABC"[:g["dim"]]]
+        fn = kron.kron2d_batched_f32 if g["dim"] == 2 else kron.kron3d_batched_f32
+        fn(g["n"], *mats, g["X"], ref, g["count"])
+        torch.cuda.synchronize()
+        assert torch.equal(ref, g["Y"]), (g["dim"], g["n"])
+
+
+def test_grouped_counters_return_to_zero():
+    """The chunk counters in the workspace are back at zero after every
+    launch (the last wavefront resets them), so launches and graph replays
+    start clean; repeated launches give the same bits."""
+    import struct
+    import paper_1304_7054_amd as kron
+    _need_gpu()
+    spec = [(2, 5, 3000), (2, 12, 800), (3, 4, 500), (3, 9, 300), (3, 16, 60)]
+    groups, host = _make_groups(spec, 31)
+    ws = torch.empty(kron.kron_grouped_workspace_size(groups), dtype=torch.uint8, device=DEV)
+    kron.kron_grouped_prepare(groups, ws)
+    first = None
+    for rep in range(5):
+        for g in groups:
+            g["Y"].fill_(float("nan"))
+        kron.kron_grouped_launch(ws)
+        torch.cuda.synchronize()
+        raw = ws.cpu().numpy().tobytes()
+        for ph in range(2):
+            counter_off = struct.unpack_from("<q", raw, 32 + 32 * ph + 24)[0]
+            nxt, done = struct.unpack_from("<QI", raw, counter_off)
+            assert (nxt, done) == (0, 0), (rep, ph, nxt, done)
+        ys = [g["Y"].clone() for g in groups]
+        if first is None:
+            _check(groups, host)
+            first = ys
+        else:
+            for a, b in zip(first, ys):
+                assert torch.equal(a, b), rep
