@@ -269,6 +269,8 @@ int kron3d_backward_f32(int n, const float* A, const float* B, const float* C, c
   if (!B) return -3;
   if (!C) return -4;
   if (int rc = check_backward<float>(3, n, X, dY, dX, dA, dB, dC, batch, ws, ws_bytes, 5)) return rc;
+  if (n == 16 && (dA || dB || dC) && kron::backward3d16_usable(X, dY, dX))
+    return finish_launch(kron::backward3d16_f32(A, B, C, X, dY, dX, dA, dB, dC, batch, ws, stream));
   if (dX && batch > 0) {
     if (int rc = finish_launch(kron::fwd3d_f32(n, A, B, C, dY, dX, batch, stream, true))) return rc;
   }

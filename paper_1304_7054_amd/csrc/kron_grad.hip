@@ -41,6 +41,32 @@ int grad_n(const typename M::io_t* A, const typename M::io_t* B, const typename 
   return 0;
 }
 
+// 3-D n = 16 FP32 with 16-byte aligned arrays: dX and the factor gradients
+// in one pass (kron3d_backward16_kernel), then the shared reduction.  The
+// workgroup count is a fixed function of the batch and the device.
+int backward3d16_f32(const float* A, const float* B, const float* C, const float* X, const float* dY, float* dX,
+                     float* dA, float* dB, float* dC, int64_t batch, void* ws, hipStream_t stream) {
+  const int which = (dA ? 1 : 0) | (dB ? 2 : 0) | (dC ? 4 : 0);
+  float* part = static_cast<float*>(ws);
+  int64_t nblocks = 0;
+  if (batch > 0) {
+    const int64_t cap = (int64_t)device_cus() * occupancy_blocks(kron3d_backward16_kernel);
+    nblocks = batch < cap ? batch : cap;
+    hipLaunchKernelGGL(kron3d_backward16_kernel, dim3((unsigned)nblocks), dim3(kGradBlock), 0, stream, A, B, C, X,
+                       dY, dX, part, batch, which);
+  }
+  if (which) {
+    hipLaunchKernelGGL((kron_grad_reduce_kernel<float, float, 16>), dim3(3), dim3(kGradBlock), 0, stream, part,
+                       nblocks, dA, dB, dC);
+  }
+  return 0;
+}
+
+bool backward3d16_usable(const void* X, const void* dY, const void* dX) {
+  const uintptr_t m = 15;
+  return (((uintptr_t)X | (uintptr_t)dY | (uintptr_t)dX) & m) == 0;
+}
+
 template <class M, int Dim>
 int grad_dispatch(int n, const typename M::io_t* A, const typename M::io_t* B, const typename M::io_t* C,
                   const typename M::io_t* X, const typename M::io_t* dY, typename M::io_t* dA,

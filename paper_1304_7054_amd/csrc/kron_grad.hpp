@@ -315,6 +315,123 @@ __global__ __launch_bounds__(kGradBlock) void kron_grad_partial_kernel(
     for (int r = 0; r < 4; ++r) ws[(wave * 3 + f) * 256 + M::drow(g, r) * 16 + L] = (T)acc[f][r];
 }
 
+// ---- fused 3-D backward for n = 16 (one operand per tile) ----------------------
+//
+// One 256-thread workgroup per tile at a time: the four wavefronts copy X and
+// dY of the tile into LDS together, then wavefronts 0, 1, 2 each accumulate
+// one factor gradient (dA, dB, dC) and wavefront 3 computes dX, the forward
+// action with every factor transposed, and stores it.  Each array is read
+// from HBM once and dX written once.  In LDS, rows of 16 elements sit at a
+// pitch of 20 and slabs at a pitch of 324 elements: rows stay 16-byte
+// aligned for the copies, and the reads along the slow axes, which the
+// gradient layouts need, fall on at most 4 lanes per bank instead of 16.
+struct Pad16 {
+  static constexpr int P1 = 20;
+  static constexpr int P0 = 16 * P1 + 4;
+  static constexpr int kElems = 16 * P0;
+  __device__ static constexpr int stride(int ax) { return ax == 0 ? P0 : ax == 1 ? P1 : 1; }
+};
+
+// The tile (4096 elements, 16-byte aligned) into its padded LDS image; every
+// thread moves 4 of the 1024 16-byte vectors, all 4 loads first.
+__device__ __forceinline__ void copy_tile16_in(const float* __restrict__ src, float* lds, int tid) {
+  f32x4 r[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) r[k] = Mem<float>::load4(src + 4 * (tid + 256 * k));
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int e = 4 * (tid + 256 * k);
+    const int off = (e >> 8) * Pad16::P0 + ((e >> 4) & 15) * Pad16::P1 + (e & 15);
+    *in_lds(reinterpret_cast<f32x4*>(lds + off)) = r[k];
+  }
+}
+
+// One factor gradient of one tile from the padded images (same layouts and
+// steps as Grad3D::tile).
+template <class M, int F>
+__device__ __forceinline__ void grad16_tile(const float* ldsX, const float* ldsY, const typename M::fac_t& fA,
+                                            const typename M::fac_t& fB, const typename M::fac_t& fC, int L, int g,
+                                            typename M::acc_t& acc) {
+  using acc_t = typename M::acc_t;
+  constexpr int lax = F, gax = F == 2 ? 1 : 2, sax = F == 0 ? 1 : 0;
+  constexpr int ygax = F == 0 ? 1 : 0, ysax = F == 2 ? 1 : 2;
+  int bx[4], by[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    bx[q] = L * Pad16::stride(lax) + (4 * g + q) * Pad16::stride(gax);
+    by[q] = L * Pad16::stride(lax) + M::drow(g, q) * Pad16::stride(ygax);
+  }
+  acc_t t[16];
+#pragma unroll
+  for (int sl = 0; sl < 16; ++sl)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) t[sl][q] = in_lds(ldsX)[bx[q] + sl * Pad16::stride(sax)];
+#pragma unroll
+  for (int sl = 0; sl < 16; ++sl) t[sl] = M::db(F == 2 ? fB : fC, t[sl]);
+  Grad3D<M, 16>::swap_rows_slabs(t);
+#pragma unroll
+  for (int sl = 0; sl < 16; ++sl) t[sl] = M::db(F == 0 ? fB : fA, t[sl]);
+#pragma unroll
+  for (int sl = 0; sl < 16; ++sl) {
+    acc_t dy;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) dy[q] = in_lds(ldsY)[by[q] + sl * Pad16::stride(ysax)];
+    acc = mma_data<M>(dy, t[sl], acc);
+  }
+}
+
+// Partials: ws[(block * 3 + f) * 256 + row * 16 + col], as the per-wavefront
+// kernel writes them (the reduction kernel is shared).  `which` bit f asks
+// for factor f's gradient; dX may be null.
+__global__ __launch_bounds__(kGradBlock) __attribute__((amdgpu_waves_per_eu(3))) void kron3d_backward16_kernel(
+    const float* __restrict__ A, const float* __restrict__ B, const float* __restrict__ C,
+    const float* __restrict__ X, const float* __restrict__ dY, float* __restrict__ dX, float* __restrict__ ws,
+    int64_t ntiles, int which) {
+  using M = ModeF32;
+  using acc_t = M::acc_t;
+  __shared__ __attribute__((aligned(16))) float sX[Pad16::kElems];
+  __shared__ __attribute__((aligned(16))) float sY[Pad16::kElems];
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, L = l & 15, g = l >> 4;
+  const bool grads = which != 0;
+  // wavefronts 0-2: factor tiles for the gradients; wavefront 3: transposed tiles for dX
+  M::fac_t fA, fB, fC;
+  if (w < 3) {
+    fA = M::load_fac<16, false>(A, L, g, 0);
+    fB = M::load_fac<16, false>(B, L, g, 0);
+    fC = M::load_fac<16, false>(C, L, g, 0);
+  }
+  const Tile3D<M, 16, false, true, true> fwd(A, B, C, L, g);
+  const bool mine = w < 3 ? (which >> w) & 1 : dX != nullptr;
+  acc_t acc = acc_t{0.f, 0.f, 0.f, 0.f};
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    __syncthreads();  // every wavefront is done with the previous tile's images
+    if (grads) copy_tile16_in(X + t * 4096, sX, tid);
+    copy_tile16_in(dY + t * 4096, sY, tid);
+    __syncthreads();
+    if (!mine) continue;
+    if (w == 0) grad16_tile<M, 0>(sX, sY, fA, fB, fC, L, g, acc);
+    else if (w == 1) grad16_tile<M, 1>(sX, sY, fA, fB, fC, L, g, acc);
+    else if (w == 2) grad16_tile<M, 2>(sX, sY, fA, fB, fC, L, g, acc);
+    else {
+      // slab a on the slow axis, L on the middle axis, slots 4g + s on the fast axis
+      acc_t v[16];
+#pragma unroll
+      for (int a = 0; a < 16; ++a) {
+        v[a] = *in_lds(reinterpret_cast<const f32x4*>(sY + a * Pad16::P0 + L * Pad16::P1 + 4 * g));
+        fwd.stage12(v[a]);
+      }
+      fwd.stage3(v);
+      float* dXt = dX + t * 4096;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) Mem<float>::store4(dXt + i * 256 + L * 16 + 4 * g, v[i]);
+    }
+  }
+  if (w < 3) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) ws[((int64_t)blockIdx.x * 3 + w) * 256 + M::drow(g, r) * 16 + L] = acc[r];
+  }
+}
+
 // dM(i, j) = sum over wavefronts (in order) and over the Q diagonal blocks of
 // the partial tiles (logical index q*n + i sits in slot slot_of(q*n + i)); one thread per entry of each requested factor; sums in
 // double.  Output column-major (i + n*j).

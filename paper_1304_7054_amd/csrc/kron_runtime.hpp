@@ -71,6 +71,11 @@ int grad2d_f32(int n, const float* A, const float* B, const float* X, const floa
                int64_t batch, void* ws, hipStream_t s);
 int grad3d_f32(int n, const float* A, const float* B, const float* C, const float* X, const float* dY, float* dA,
                float* dB, float* dC, int64_t batch, void* ws, hipStream_t s);
+// 3-D n = 16 FP32 backward in one pass (dX and the factor gradients); usable
+// when X, dY and dX (if given) are 16-byte aligned.
+int backward3d16_f32(const float* A, const float* B, const float* C, const float* X, const float* dY, float* dX,
+                     float* dA, float* dB, float* dC, int64_t batch, void* ws, hipStream_t stream);
+bool backward3d16_usable(const void* X, const void* dY, const void* dX);
 int grad2d_f64(int n, const double* A, const double* B, const double* X, const double* dY, double* dA, double* dB,
                int64_t batch, void* ws, hipStream_t s);
 int grad3d_f64(int n, const double* A, const double* B, const double* C, const double* X, const double* dY,

@@ -179,3 +179,43 @@ def test_mixed_shapes_finite_differences_fp64():
             xm[e] -= h
             fd = (L(xp.view_as(X), [m.detach() for m in mats]) - L(xm.view_as(X), [m.detach() for m in mats])) / (2 * h)
             assert abs(gx[e] - fd) <= 1e-8 * (1 + abs(fd)), (dim, n, e)
+
+
+@pytest.mark.parametrize("want", [(True, True, True, True), (False, True, False, False), (True, False, True, True),
+                                  (False, False, False, True)])
+def test_fused_16_backward_subsets_and_unfused_agree(want):
+    """3-D n = 16 FP32 takes the one-pass backward (dX and the factor
+    gradients from one read of X and dY) when the arrays are 16-byte aligned;
+    a batch above the workgroup count runs several tiles per workgroup.
+    Requested outputs match the FP64 oracle, skipped ones stay untouched, and
+    the unfused path (reached through arrays one element off alignment)
+    agrees within the FP32 tolerance."""
+    _need_gpu()
+    import paper_1304_7054_amd as kron
+    n, batch = 16, 2000
+    rng = np.random.default_rng(61)
+    mats = [rng.uniform(-1, 1, n * n).astype(np.float32) for _ in range(3)]
+    X = rng.standard_normal(batch * n ** 3).astype(np.float32)
+    dY = rng.standard_normal(batch * n ** 3).astype(np.float32)
+    ref = _oracle_grad(3, n, [m.astype(np.float64) for m in mats], X.astype(np.float64), dY.astype(np.float64), batch)
+    got = _abi_backward(3, n, mats, X, dY, batch, np.float32, want=want)
+    for name, w, g, r in zip(["dX", "dA", "dB", "dC"], want, got, ref):
+        if w:
+            assert np.all(np.isfinite(g)) and _rel(g, r) <= 1e-5, (name, _rel(g, r))
+        else:
+            assert g is None
+    # the same call on arrays that start one element past an aligned address
+    tm = [torch.from_numpy(m).to(DEV) for m in mats]
+    xb = torch.empty(X.size + 1, device=DEV)
+    yb = torch.empty(X.size + 1, device=DEV)
+    xb[1:] = torch.from_numpy(X).to(DEV)
+    yb[1:] = torch.from_numpy(dY).to(DEV)
+    dxb = torch.full((X.size + 1,), float("nan"), device=DEV) if want[0] else None
+    grads = [torch.full((n * n,), float("nan"), device=DEV) if w else None for w in want[1:]]
+    ws = torch.empty(kron.kron_backward_workspace_size(3, n, batch, kron.MODE_F32), dtype=torch.uint8, device=DEV)
+    kron.kron3d_backward_f32(n, *tm, xb[1:], yb[1:], dxb[1:] if dxb is not None else None, *grads, batch, ws)
+    torch.cuda.synchronize()
+    other = [dxb[1:].cpu().numpy() if dxb is not None else None] + [gg.cpu().numpy() if gg is not None else None for gg in grads]
+    for name, a, b in zip(["dX", "dA", "dB", "dC"], got, other):
+        if a is not None:
+            assert _rel(a, b) <= 2e-6, (name, _rel(a, b))
