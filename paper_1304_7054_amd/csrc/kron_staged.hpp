@@ -209,14 +209,67 @@ struct Staged3D {
   }
 };
 
-// One tile through an LDS slice of S::kSlice elements (16-byte aligned).  Packed
-// tiles (several operands) whose result holds a non-finite value are redone
-// one operand at a time: the slice is zeroed, only operand o is copied in (at
-// its own place), the same code runs, and only operand o is copied out, so
-// IEEE propagation stays inside operand o.
-template <class S>
+// Prefetch of a run of operands into registers: the run's head elements
+// (up to the first 16-byte boundary), its first kPre 16-byte vectors per lane
+// and its tail elements are loaded by issue(); commit() writes them into an
+// LDS slice placed at the run's 16-byte phase (stage_base) and copies any
+// vectors beyond the first 64 * kPre directly.  Issued for the next tile
+// before the current one is computed, the loads overlap that work.
+template <typename io_t, int kMaxElems>
+struct RunPrefetch {
+  static constexpr int V = 16 / (int)sizeof(io_t);
+  static constexpr int kAll = (kMaxElems / V + 63) / 64;
+  static constexpr int kPre = kAll < 8 ? kAll : 8;
+  u32x4 r[kPre];
+  io_t hv, tv;
+  const io_t* src;
+  int count, head, nv;
+
+  __device__ __forceinline__ void issue(const io_t* src_, int count_, int lane) {
+    src = src_;
+    count = count_;
+    head = head_elems(src, count);
+    nv = (count - head) / V;
+    const u32x4* s4 = reinterpret_cast<const u32x4*>(src + head);
+    if (lane < head) hv = __builtin_nontemporal_load(in_global(src) + lane);
+#pragma unroll
+    for (int k = 0; k < kPre; ++k) {
+      const int i = lane + 64 * k;
+      if (i < nv) r[k] = __builtin_nontemporal_load(in_global(s4) + i);
+    }
+    const int done = head + nv * V;
+    if (lane < count - done) tv = __builtin_nontemporal_load(in_global(src) + done + lane);
+  }
+
+  // lds: the slice base for this run (stage_base(slice, src))
+  __device__ __forceinline__ void commit(io_t* lds, int lane) const {
+    u32x4* d4 = reinterpret_cast<u32x4*>(lds + head);
+    if (lane < head) in_lds(lds)[lane] = hv;
+#pragma unroll
+    for (int k = 0; k < kPre; ++k) {
+      const int i = lane + 64 * k;
+      if (i < nv) in_lds(d4)[i] = r[k];
+    }
+    if constexpr (kAll > kPre) {
+      const u32x4* s4 = reinterpret_cast<const u32x4*>(src + head);
+      batched_in<u32x4, 8>(s4 + 64 * kPre, d4 + 64 * kPre, nv - 64 * kPre, lane);
+    }
+    const int done = head + nv * V;
+    if (lane < count - done) in_lds(lds)[done + lane] = tv;
+  }
+};
+
+// One tile through an LDS slice of S::kSlice elements (16-byte aligned).
+// Packed tiles (several operands) whose result holds a non-finite value are
+// redone one operand at a time: the slice is zeroed, only operand o is copied
+// in (at its own place), the same code runs, and only operand o is copied
+// out, so IEEE propagation stays inside operand o.  With kPf the tile's
+// operands come from the prefetch `pf` (issued earlier), and the prefetch of
+// the next tile (Xnext, if not null) is issued once this one sits in LDS.
+template <class S, bool kPf = false, class P = RunPrefetch<typename S::io_t, 1>>
 __device__ __forceinline__ void staged3d_tile(const S& st, typename S::io_t* slice, const typename S::io_t* Xt,
-                                              typename S::io_t* Yt, int64_t rem, int l) {
+                                              typename S::io_t* Yt, int64_t rem, int l, P* pf = nullptr,
+                                              const typename S::io_t* Xnext = nullptr, int64_t rem_next = 0) {
   using acc_t = typename S::acc_t;
   typename S::io_t* lds = stage_base(slice, Xt);
   const int nops = (int)(rem < S::kOps ? rem : S::kOps);
@@ -227,9 +280,16 @@ __device__ __forceinline__ void staged3d_tile(const S& st, typename S::io_t* sli
     wave_sync_lds();  // the previous copy-out has read the slice
     if (o >= 0) zero_fill(lds, 0, S::kElems, l);
     else zero_fill(lds, count, S::kElems, l);
+    if (kPf && o < 0) {
+      pf->commit(lds, l);
+    } else {
+      wave_sync_lds();
+      copy_in(Xt + first, lds + first, count, l);
+    }
     wave_sync_lds();
-    copy_in(Xt + first, lds + first, count, l);
-    wave_sync_lds();
+    if constexpr (kPf) {
+      if (o < 0 && Xnext) pf->issue(Xnext, (int)(rem_next < S::kOps ? rem_next : S::kOps) * S::E, l);
+    }
     acc_t v[16];
 #pragma unroll
     for (int a = 0; a < 16; ++a) {
@@ -272,8 +332,23 @@ __global__ __launch_bounds__(kBlock) void kron3d_staged_kernel(const typename M:
   const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * kBlock) >> 6;
   const S st(A, B, C, L, g);
-  for (int64_t t = wave; t < ntiles; t += nwaves)
-    staged3d_tile(st, lds, X + t * S::kElems, Y + t * S::kElems, batch - t * S::kOps, l);
+  using P = RunPrefetch<io_t, S::kElems>;
+  if constexpr (P::kAll <= 4) {
+    // small tiles: the next tile's operands (at most 4 vectors per lane) are
+    // loaded while the current one is computed; larger tiles would give up
+    // occupancy for the registers
+    P pf;
+    int64_t t = wave;
+    if (t < ntiles) pf.issue(X + t * S::kElems, (int)((batch - t * S::kOps) < S::kOps ? batch - t * S::kOps : S::kOps) * S::E, l);
+    for (; t < ntiles; t += nwaves) {
+      const int64_t tn = t + nwaves;
+      staged3d_tile<S, true>(st, lds, X + t * S::kElems, Y + t * S::kElems, batch - t * S::kOps, l, &pf,
+                             tn < ntiles ? X + tn * S::kElems : nullptr, batch - tn * S::kOps);
+    }
+  } else {
+    for (int64_t t = wave; t < ntiles; t += nwaves)
+      staged3d_tile(st, lds, X + t * S::kElems, Y + t * S::kElems, batch - t * S::kOps, l);
+  }
 }
 
 // ---- 2-D (X: L on the slow axis, slots 4g + s on the fast axis; Y: L on the
