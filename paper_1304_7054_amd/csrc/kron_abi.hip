@@ -52,13 +52,17 @@ LaunchShape default_shape(int mode, int dim, int n) {
   }
   if (dim == 3) {
     switch (mode) {
-      case 0: return LaunchShape{0, 9};   // FP32: stores interleaved with the next tile, 2-slab window
-      case 1: return LaunchShape{2, 7};   // FP64: 4-slab window + next tile, 2 workgroups per CU
-      case 2: return LaunchShape{0, 10};  // bf16x3: stores interleaved, 4-slab window
-      default: return LaunchShape{0, 5};  // bf16 storage: contiguous rows, 4-slab window
+      case 0: return LaunchShape{2, 9};   // FP32: stores interleaved with the next tile, 2-slab window
+      case 1: return LaunchShape{2, 7};   // FP64: 4-slab window + next tile
+      case 2: return LaunchShape{2, 9};   // bf16x3: as FP32
+      default: return LaunchShape{0, 10}; // bf16 storage: stores interleaved, 4-slab window
     }
   }
-  return LaunchShape{0, 0};
+  switch (mode) {
+    case 0: return LaunchShape{2, 0};  // FP32 2-D: 4 tiles in flight, 2 workgroups per CU
+    case 1: return LaunchShape{3, 1};  // FP64 2-D: 8 tiles in flight, 3 workgroups per CU
+    default: return LaunchShape{0, 0};
+  }
 }
 }  // namespace
 

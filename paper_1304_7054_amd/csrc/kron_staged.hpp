@@ -317,8 +317,16 @@ __device__ __forceinline__ void staged3d_tile(const S& st, typename S::io_t* sli
   }
 }
 
+// Waves per SIMD the 3-D staged kernel is held to: single-operand tiles for
+// n = 9 .. 13 fit four (their LDS slices are small); the larger tiles are
+// limited by LDS to two anyway and are left unconstrained (1).
+template <int N>
+constexpr int staged3d_waves() {
+  return N >= 9 && N <= 13 ? 4 : 1;
+}
+
 template <class M, int N, bool kTrans>
-__global__ __launch_bounds__(kBlock) void kron3d_staged_kernel(const typename M::io_t* __restrict__ A,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(staged3d_waves<N>()))) void kron3d_staged_kernel(const typename M::io_t* __restrict__ A,
                                                                const typename M::io_t* __restrict__ B,
                                                                const typename M::io_t* __restrict__ C,
                                                                const typename M::io_t* __restrict__ X,
@@ -399,25 +407,37 @@ struct Staged2D {
 // piece, the tail of the span zero-filled, and the results copied out as one
 // piece.  A packed tile with a non-finite result is redone per operand as in
 // 3-D; its span part is then left out of the copy-out.
+// Operands in the span of tiles t0 .. min(t0 + kT, last) - 1.
 template <class S>
+__device__ __forceinline__ int span_elems(int64_t t0, int64_t last, int64_t batch) {
+  const int64_t ops_left = batch - t0 * S::kOps;
+  const int64_t tiles_left = last - t0;
+  const int64_t cap = (tiles_left < S::kT ? tiles_left : S::kT) * S::kOps;
+  return (int)(ops_left < cap ? ops_left : cap) * S::E;
+}
+
+// With kPf the span's operands come from the prefetch `pf`, and the next
+// span (tile tn, if tn < last) is prefetched once this one sits in LDS.
+template <class S, bool kPf = false, class P = RunPrefetch<typename S::io_t, 1>>
 __device__ __forceinline__ void staged2d_tiles(const S& st, typename S::io_t* span, const typename S::io_t* X,
                                                typename S::io_t* Y, int64_t t0, int64_t last, int64_t batch,
-                                               int l) {
+                                               int l, P* pf = nullptr, int64_t tn = 0) {
   using io_t = typename S::io_t;
   using acc_t = typename S::acc_t;
   constexpr int kT = S::kT;
-  const int64_t ops_left = batch - t0 * S::kOps;
-  const int64_t tiles_left = last - t0;
-  const int64_t cap = (tiles_left < kT ? tiles_left : kT) * S::kOps;
-  const int nops_all = (int)(ops_left < cap ? ops_left : cap);
-  const int count = nops_all * S::E;
+  const int count = span_elems<S>(t0, last, batch);
+  const int nops_all = count / S::E;
   const io_t* Xs = X + t0 * S::kElems;
   io_t* Ys = Y + t0 * S::kElems;
   span = stage_base(span, Xs);
   wave_sync_lds();
   zero_fill(span, count, kT * S::kElems, l);
-  copy_in(Xs, span, count, l);
+  if constexpr (kPf) pf->commit(span, l);
+  else copy_in(Xs, span, count, l);
   wave_sync_lds();
+  if constexpr (kPf) {
+    if (tn < last) pf->issue(X + tn * S::kElems, span_elems<S>(tn, last, batch), l);
+  }
   acc_t v[kT];
 #pragma unroll
   for (int j = 0; j < kT; ++j) v[j] = st.tile.compute(st.read(span + j * S::kElems));
@@ -468,7 +488,7 @@ __device__ __forceinline__ void staged2d_tiles(const S& st, typename S::io_t* sp
 }
 
 template <class M, int N, bool kTrans>
-__global__ __launch_bounds__(kBlock) void kron2d_staged_kernel(const typename M::io_t* __restrict__ A,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void kron2d_staged_kernel(const typename M::io_t* __restrict__ A,
                                                                const typename M::io_t* __restrict__ B,
                                                                const typename M::io_t* __restrict__ X,
                                                                typename M::io_t* __restrict__ Y, int64_t batch,
@@ -482,8 +502,13 @@ __global__ __launch_bounds__(kBlock) void kron2d_staged_kernel(const typename M:
   const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * kBlock) >> 6;
   const S st(A, B, L, g);
-  for (int64_t base = wave * kT; base < ntiles; base += nwaves * kT)
-    staged2d_tiles<S>(st, mine, X, Y, base, ntiles, batch, l);
+  // the next span's operands (at most about 4 KiB) are loaded while the
+  // current span is computed and written out
+  RunPrefetch<io_t, kT * S::kElems> pf;
+  int64_t base = wave * kT;
+  if (base < ntiles) pf.issue(X + base * S::kElems, span_elems<S>(base, ntiles, batch), l);
+  for (; base < ntiles; base += nwaves * kT)
+    staged2d_tiles<S, true>(st, mine, X, Y, base, ntiles, batch, l, &pf, base + nwaves * kT);
 }
 
 }  // namespace kron
