@@ -362,21 +362,42 @@ __device__ __forceinline__ void grad16_tile(const float* ldsX, const float* ldsY
     by[q] = L * Pad16::stride(lax) + M::drow(g, q) * Pad16::stride(ygax);
   }
   acc_t t[16];
+  if constexpr (gax == 2) {
+    // the four slots 4g .. 4g + 3 are consecutive, 16-byte aligned elements
 #pragma unroll
-  for (int sl = 0; sl < 16; ++sl)
+    for (int sl = 0; sl < 16; ++sl) t[sl] = *in_lds(reinterpret_cast<const acc_t*>(ldsX + bx[0] + sl * Pad16::stride(sax)));
+  } else {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) t[sl][q] = in_lds(ldsX)[bx[q] + sl * Pad16::stride(sax)];
+    for (int sl = 0; sl < 16; ++sl)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) t[sl][q] = in_lds(ldsX)[bx[q] + sl * Pad16::stride(sax)];
+  }
 #pragma unroll
   for (int sl = 0; sl < 16; ++sl) t[sl] = M::db(F == 2 ? fB : fC, t[sl]);
   Grad3D<M, 16>::swap_rows_slabs(t);
 #pragma unroll
   for (int sl = 0; sl < 16; ++sl) t[sl] = M::db(F == 0 ? fB : fA, t[sl]);
+  if constexpr (ysax == 2) {
+    // four consecutive slabs of one slot are consecutive, 16-byte aligned elements
 #pragma unroll
-  for (int sl = 0; sl < 16; ++sl) {
-    acc_t dy;
+    for (int s4 = 0; s4 < 16; s4 += 4) {
+      acc_t quad[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) dy[q] = in_lds(ldsY)[by[q] + sl * Pad16::stride(ysax)];
-    acc = mma_data<M>(dy, t[sl], acc);
+      for (int q = 0; q < 4; ++q) quad[q] = *in_lds(reinterpret_cast<const acc_t*>(ldsY + by[q] + s4));
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const acc_t dy = acc_t{quad[0][j], quad[1][j], quad[2][j], quad[3][j]};
+        acc = mma_data<M>(dy, t[s4 + j], acc);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int sl = 0; sl < 16; ++sl) {
+      acc_t dy;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) dy[q] = in_lds(ldsY)[by[q] + sl * Pad16::stride(ysax)];
+      acc = mma_data<M>(dy, t[sl], acc);
+    }
   }
 }
 
