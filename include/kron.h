@@ -197,8 +197,8 @@ int kron3d_backward_f64(int n, const double* A, const double* B, const double* C
      3-D: 0 plain; 1 next tile prefetched; 2 contiguous 1 KiB rows (a second
           register exchange); 3 = 1 + 2; 4/5 = contiguous rows with a window
           of 2/4 slab loads in flight; 6/7 = 4/5 with the next tile's first
-          slabs requested early; 8 = tiles staged through LDS (n != 16, FP32,
-          bf16x3 and bf16 storage; otherwise variant 0); 9/10 = n = 16,
+          slabs requested early; 8 = tiles staged through LDS (n != 16;
+          otherwise variant 0); 9/10 = n = 16,
           contiguous rows, the result stores interleaved with the next
           tile's slab loads (window 2/4; otherwise variant 4).  The paper
    picks its kernel method by matrix size and fixes the number of thread

@@ -45,11 +45,7 @@ void init_shapes() {
 // Built-in defaults, measured on MI355X at n = 16 with 1 GiB batches (the
 // autotuner refines them per n).
 LaunchShape default_shape(int mode, int dim, int n) {
-  if (n != 16) {
-    // staged through LDS (3-D only for elements of at most 4 bytes)
-    if (dim == 2) return LaunchShape{0, 3};
-    if (mode != 1) return LaunchShape{0, 8};
-  }
+  if (n != 16) return LaunchShape{0, dim == 2 ? 3 : 8};  // staged through LDS
   if (dim == 3) {
     switch (mode) {
       case 0: return LaunchShape{2, 9};   // FP32: stores interleaved with the next tile, 2-slab window

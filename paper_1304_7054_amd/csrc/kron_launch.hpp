@@ -70,10 +70,10 @@ void launch2d_v(int variant, const typename M::io_t* A, const typename M::io_t* 
   }
 }
 
-// Sizes that read their tiles through LDS (every n but 16; 3-D only for
-// elements of at most 4 bytes, whose slices fit 64 KiB per workgroup).
+// Sizes that read their tiles through LDS: every n but 16 (an FP64 3-D
+// slice is up to 32 KiB per wavefront, 128 KiB per workgroup).
 template <class M, int N, int Dim>
-constexpr bool kStageable = N != 16 && (Dim == 2 || sizeof(typename M::io_t) <= 4);
+constexpr bool kStageable = N != 16;
 
 // 2-D variants: tiles kept in flight per wavefront, 0 -> 4, 1 -> 8, 2 -> 2;
 // 3 -> tiles staged through LDS (n != 16).
@@ -159,8 +159,7 @@ void launch3d_v(int variant, const typename M::io_t* A, const typename M::io_t* 
 // (operand slabs along the slow axis, a second lane-group exchange),
 // 3 = 1 + 2, 4/5 contiguous rows with a window of 2/4 slab loads in flight,
 // 6/7 = 4/5 with the next tile's first slabs requested before stage 3,
-// 8 = tiles staged through LDS (n != 16, elements of at most 4 bytes; other
-// sizes fall back to variant 0), 9/10 = n = 16 with the result stores
+// 8 = tiles staged through LDS (n != 16; n = 16 falls back to variant 0), 9/10 = n = 16 with the result stores
 // interleaved with the next tile's loads and stages 1-2, window 2/4 (other
 // sizes and unaligned arrays run variant 4, the same stage order).
 template <class M, int N, bool kTrans>

@@ -235,7 +235,7 @@ def test_launch_variants_agree(mode, dim, n):
             # with the next tile, n = 16; variant 4 otherwise) contract C, B,
             # A; 0 and 1 contract C, A, B.  Variant 8 at a size it cannot
             # use runs variant 0.
-            stageable = n != 16 and mode != "f64"
+            stageable = n != 16
             if dim == 2:
                 order = 0
             elif variant == 8:
