@@ -332,12 +332,15 @@ struct Pad16 {
   __device__ static constexpr int stride(int ax) { return ax == 0 ? P0 : ax == 1 ? P1 : 1; }
 };
 
-// The tile (4096 elements, 16-byte aligned) into its padded LDS image; every
-// thread moves 4 of the 1024 16-byte vectors, all 4 loads first.
-__device__ __forceinline__ void copy_tile16_in(const float* __restrict__ src, float* lds, int tid) {
-  f32x4 r[4];
+// A tile (4096 elements, 16-byte aligned) moves into its padded LDS image
+// in two steps, so that the loads of the next tile can be in flight while
+// the current one is computed: every thread loads 4 of the 1024 16-byte
+// vectors into registers, and later writes them to their padded places.
+__device__ __forceinline__ void load_tile16(const float* __restrict__ src, f32x4 (&r)[4], int tid) {
 #pragma unroll
   for (int k = 0; k < 4; ++k) r[k] = Mem<float>::load4(src + 4 * (tid + 256 * k));
+}
+__device__ __forceinline__ void store_tile16(const f32x4 (&r)[4], float* lds, int tid) {
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const int e = 4 * (tid + 256 * k);
@@ -377,6 +380,11 @@ __device__ __forceinline__ void grad16_tile(const float* ldsX, const float* ldsY
   Grad3D<M, 16>::swap_rows_slabs(t);
 #pragma unroll
   for (int sl = 0; sl < 16; ++sl) t[sl] = M::db(F == 0 ? fB : fA, t[sl]);
+  // four independent accumulators (slab mod 4) keep the matrix-core pipe fed
+  // instead of one dependent chain of 64 products; summed in a fixed order
+  acc_t part[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) part[j] = acc_t{0.f, 0.f, 0.f, 0.f};
   if constexpr (ysax == 2) {
     // four consecutive slabs of one slot are consecutive, 16-byte aligned elements
 #pragma unroll
@@ -387,7 +395,7 @@ __device__ __forceinline__ void grad16_tile(const float* ldsX, const float* ldsY
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const acc_t dy = acc_t{quad[0][j], quad[1][j], quad[2][j], quad[3][j]};
-        acc = mma_data<M>(dy, t[s4 + j], acc);
+        part[j] = mma_data<M>(dy, t[s4 + j], part[j]);
       }
     }
   } else {
@@ -396,15 +404,16 @@ __device__ __forceinline__ void grad16_tile(const float* ldsX, const float* ldsY
       acc_t dy;
 #pragma unroll
       for (int q = 0; q < 4; ++q) dy[q] = in_lds(ldsY)[by[q] + sl * Pad16::stride(ysax)];
-      acc = mma_data<M>(dy, t[sl], acc);
+      part[sl & 3] = mma_data<M>(dy, t[sl], part[sl & 3]);
     }
   }
+  acc += (part[0] + part[1]) + (part[2] + part[3]);
 }
 
 // Partials: ws[(block * 3 + f) * 256 + row * 16 + col], as the per-wavefront
 // kernel writes them (the reduction kernel is shared).  `which` bit f asks
 // for factor f's gradient; dX may be null.
-__global__ __launch_bounds__(kGradBlock) __attribute__((amdgpu_waves_per_eu(3))) void kron3d_backward16_kernel(
+__global__ __launch_bounds__(kGradBlock) __attribute__((amdgpu_waves_per_eu(2))) void kron3d_backward16_kernel(
     const float* __restrict__ A, const float* __restrict__ B, const float* __restrict__ C,
     const float* __restrict__ X, const float* __restrict__ dY, float* __restrict__ dX, float* __restrict__ ws,
     int64_t ntiles, int which) {
@@ -414,25 +423,33 @@ __global__ __launch_bounds__(kGradBlock) __attribute__((amdgpu_waves_per_eu(3)))
   __shared__ __attribute__((aligned(16))) float sY[Pad16::kElems];
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, L = l & 15, g = l >> 4;
   const bool grads = which != 0;
-  // wavefronts 0-2: factor tiles for the gradients; wavefront 3: transposed tiles for dX
-  M::fac_t fA, fB, fC;
-  if (w < 3) {
-    fA = M::load_fac<16, false>(A, L, g, 0);
-    fB = M::load_fac<16, false>(B, L, g, 0);
-    fC = M::load_fac<16, false>(C, L, g, 0);
-  }
+  const M::fac_t fA = M::load_fac<16, false>(A, L, g, 0);
+  const M::fac_t fB = M::load_fac<16, false>(B, L, g, 0);
+  const M::fac_t fC = M::load_fac<16, false>(C, L, g, 0);
   const Tile3D<M, 16, false, true, true> fwd(A, B, C, L, g);
-  const bool mine = w < 3 ? (which >> w) & 1 : dX != nullptr;
-  acc_t acc = acc_t{0.f, 0.f, 0.f, 0.f};
-  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+  acc_t acc[3];
+#pragma unroll
+  for (int f = 0; f < 3; ++f) acc[f] = acc_t{0.f, 0.f, 0.f, 0.f};
+  int role = w;  // rotates by one per tile, so every SIMD takes every role in turn
+  f32x4 px[4], py[4];  // the next tile's X and dY, in flight while the current tile is computed
+  if (blockIdx.x < ntiles) {
+    if (grads) load_tile16(X + blockIdx.x * 4096, px, tid);
+    load_tile16(dY + blockIdx.x * 4096, py, tid);
+  }
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x, role = (role + 1) & 3) {
     __syncthreads();  // every wavefront is done with the previous tile's images
-    if (grads) copy_tile16_in(X + t * 4096, sX, tid);
-    copy_tile16_in(dY + t * 4096, sY, tid);
+    if (grads) store_tile16(px, sX, tid);
+    store_tile16(py, sY, tid);
     __syncthreads();
-    if (!mine) continue;
-    if (w == 0) grad16_tile<M, 0>(sX, sY, fA, fB, fC, L, g, acc);
-    else if (w == 1) grad16_tile<M, 1>(sX, sY, fA, fB, fC, L, g, acc);
-    else if (w == 2) grad16_tile<M, 2>(sX, sY, fA, fB, fC, L, g, acc);
+    const int64_t tn = t + gridDim.x;
+    if (tn < ntiles) {
+      if (grads) load_tile16(X + tn * 4096, px, tid);
+      load_tile16(dY + tn * 4096, py, tid);
+    }
+    if (role < 3 ? !((which >> role) & 1) : dX == nullptr) continue;
+    if (role == 0) grad16_tile<M, 0>(sX, sY, fA, fB, fC, L, g, acc[0]);
+    else if (role == 1) grad16_tile<M, 1>(sX, sY, fA, fB, fC, L, g, acc[1]);
+    else if (role == 2) grad16_tile<M, 2>(sX, sY, fA, fB, fC, L, g, acc[2]);
     else {
       // slab a on the slow axis, L on the middle axis, slots 4g + s on the fast axis
       acc_t v[16];
@@ -447,9 +464,20 @@ __global__ __launch_bounds__(kGradBlock) __attribute__((amdgpu_waves_per_eu(3)))
       for (int i = 0; i < 16; ++i) Mem<float>::store4(dXt + i * 256 + L * 16 + 4 * g, v[i]);
     }
   }
-  if (w < 3) {
+  // the four wavefronts' partials, summed in wavefront order through LDS
+  __syncthreads();
+  float* red = sX;  // 4 x 3 x 256 floats
 #pragma unroll
-    for (int r = 0; r < 4; ++r) ws[((int64_t)blockIdx.x * 3 + w) * 256 + M::drow(g, r) * 16 + L] = acc[r];
+  for (int f = 0; f < 3; ++f)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) in_lds(red)[(w * 3 + f) * 256 + M::drow(g, r) * 16 + L] = acc[f][r];
+  __syncthreads();
+  for (int e = tid; e < 3 * 256; e += kGradBlock) {
+    const int f = e >> 8, idx = e & 255;
+    float sum = 0.f;
+#pragma unroll
+    for (int ww = 0; ww < 4; ++ww) sum += in_lds(red)[(ww * 3 + f) * 256 + idx];
+    ws[((int64_t)blockIdx.x * 3 + f) * 256 + idx] = sum;
   }
 }
 
