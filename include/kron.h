@@ -131,17 +131,23 @@ typedef struct kron_group {
 } kron_group_t;
 
 /* The batched action of Section 2.2 over a batch that mixes sizes and 2-D /
-   3-D operands, in ONE persistent kernel launch (so one graph node).
-   kron_grouped_prepare builds the work plan on the host (groups cut into
-   runs of tiles of about equal cost, runs handed to wavefronts largest
-   first) and copies it into `ws`, caller-owned device memory of at least
-   kron_grouped_workspace_size() bytes; it synchronises `stream`.  The plan
-   keeps the group pointers: the arrays must stay valid while it is used.
-   kron_grouped_launch(ws) then runs every group; it is asynchronous, takes
-   no host-side work besides the launch, and can be captured in a HIP graph.
-   The plan is bound to this process and to the device it was prepared on;
-   preparing the same `ws` again replaces it.  Returns 0 or -k (argument k
-   invalid: -1 also for any bad group descriptor; -4 workspace too small). */
+   3-D operands, in two persistent kernel launches (2-D groups, then 3-D
+   groups; one graph capture holds both).  kron_grouped_prepare builds the
+   plan on the host and copies it into `ws`, caller-owned device memory of
+   at least kron_grouped_workspace_size() bytes; it synchronises `stream`.
+   The plan orders each phase's groups, cuts their tiles into chunks that
+   shrink towards the end of the sequence, and holds one counter per phase
+   from which the kernels' wavefronts claim chunks; the last wavefront of a
+   launch resets the counter, so every launch (and graph replay) starts from
+   the prepared state.  Launches that share one `ws` must therefore be
+   ordered (same stream, or synchronised): concurrent ones race on the
+   counter.  Results do not depend on which wavefront ran which chunk.  The
+   plan keeps the group pointers: the arrays must stay valid while it is
+   used.  kron_grouped_launch(ws) runs every group; it is asynchronous and
+   takes no host-side work besides the launches.  The plan is bound to this
+   process and to the device it was prepared on; preparing the same `ws`
+   again replaces it.  Returns 0 or -k (argument k invalid: -1 also for any
+   bad group descriptor; -4 workspace too small). */
 size_t kron_grouped_workspace_size(const kron_group_t* groups, int ngroups);
 int kron_grouped_prepare(const kron_group_t* groups, int ngroups, void* ws, size_t ws_bytes,
                          hipStream_t stream);
@@ -169,10 +175,13 @@ int kron_graph_destroy(void* graph_exec);
    overwritten (zero for batch == 0).  Any of dX, dA, dB, dC may be NULL to
    skip it; X may be NULL when only dX is wanted.  dX must not alias X or dY.
    `ws` is caller-owned device memory of at least
-   kron_backward_workspace_size(dim, n, batch, mode) bytes (per-wavefront
-   partial sums; needed only for dA/dB/dC).  The summation order is fixed, so
-   repeated calls on the same device give identical bits.  FP32 partial sums,
-   final sums in FP64.  Asynchronous on `stream`. */
+   kron_backward_workspace_size(dim, n, batch, mode) bytes (per-wavefront or
+   per-workgroup partial sums; needed only for dA/dB/dC).  For 3-D n = 16
+   FP32 with 16-byte aligned X, dY and dX and at least one factor gradient
+   requested, dX and the factor gradients come from one pass over X and dY.
+   The summation order is fixed, so repeated calls on the same device give
+   identical bits.  FP32 partial sums, final sums in FP64.  Asynchronous on
+   `stream`. */
 size_t kron_backward_workspace_size(int dim, int n, int64_t batch, int mode);
 int kron2d_backward_f32(int n, const float* A, const float* B, const float* X, const float* dY,
                         float* dX, float* dA, float* dB, int64_t batch, void* ws, size_t ws_bytes,
