@@ -43,6 +43,9 @@ def parse():
     p.add_argument("--summarize-profiles", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
                    help="read rocprofv3 outputs of this script (kernel trace, FETCH_SIZE, WRITE_SIZE runs "
                         "with --copy-calibration) and write the summary and traffic record under profiles/")
+    p.add_argument("--summarize-trace", metavar="TRACE_DIR",
+                   help="read a rocprofv3 --kernel-trace --stats run of the whole benchmark and write the per-kernel "
+                        "summary profiles/bench_kernels.md")
     p.add_argument("--copy-calibration", action="store_true",
                    help="first run three plain 1 GiB device copies (a kernel of known traffic for "
                         "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -335,6 +338,45 @@ python bench.py --summarize-profiles gpurun_out/prof_trace gpurun_out/prof_fetch
 """
 
 
+TRACE_COMMAND = ("rocprofv3 --kernel-trace --stats -d gpurun_out/prof_all -o all --output-format csv -- "
+                 "python bench.py --no-cpu --device-warm 0.2 --steps 20")
+
+
+def summarize_trace(trace_dir):
+    """Per-kernel durations of the library's kernels over a traced run of the
+    whole benchmark (every mode, the grouped launch and the backward)."""
+    stats = _csv(trace_dir, "kernel_stats.csv")
+    rows = [r for r in stats if "kron" in r["Name"]]
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    lines = [
+        "# Kernel durations over the whole benchmark run",
+        "",
+        "Every `kron` kernel launched by `bench.py` (all modes, the grouped launch, the backward), from one",
+        "rocprofv3 kernel trace. The call counts include the untimed warm-up launches; averages are per dispatch",
+        "under the profiler.",
+        "",
+        "```",
+        "export TMPDIR=/tmp",
+        TRACE_COMMAND,
+        f"python bench.py --summarize-trace gpurun_out/prof_all",
+        "```",
+        "",
+        "| kernel | calls | avg us | min us | max us |",
+        "|---|---|---|---|---|",
+    ]
+    for r in rows:
+        name = r["Name"].replace("void ", "")
+        if name.endswith(")"):
+            name = name[:name.rfind("(")]  # drop the parameter list
+        lines.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                     f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} |")
+    lines.append("")
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    with open(os.path.join(ROOT, "profiles", "bench_kernels.md"), "w") as f:
+        f.write("\n".join(lines))
+    print("\n".join(lines))
+
+
 def _profile_markdown(out, stats):
     rows = sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:5]
     lines = [
@@ -392,6 +434,9 @@ def main():
     DEVICE_WARM_S = max(0.0, args.device_warm)
     if args.summarize_profiles:
         summarize_profiles(*args.summarize_profiles)
+        return
+    if args.summarize_trace:
+        summarize_trace(args.summarize_trace)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "

@@ -36,8 +36,8 @@ int grad_n(const typename M::io_t* A, const typename M::io_t* B, const typename 
     hipLaunchKernelGGL((kron_grad_partial_kernel<M, N, Dim>), dim3((unsigned)(nwaves / 4)), dim3(kGradBlock), 0,
                        stream, A, B, C, X, dY, part, batch, ntiles, which);
   }
-  hipLaunchKernelGGL((kron_grad_reduce_kernel<typename M::io_t, T, N>), dim3(3), dim3(kGradBlock), 0, stream, part,
-                     nwaves, dA, dB, dC);
+  hipLaunchKernelGGL((kron_grad_reduce_kernel<typename M::io_t, T, N>), dim3(3 * N * N), dim3(kGradBlock), 0, stream,
+                     part, nwaves, dA, dB, dC);
   return 0;
 }
 
@@ -56,8 +56,8 @@ int backward3d16_f32(const float* A, const float* B, const float* C, const float
                        dY, dX, part, batch, which);
   }
   if (which) {
-    hipLaunchKernelGGL((kron_grad_reduce_kernel<float, float, 16>), dim3(3), dim3(kGradBlock), 0, stream, part,
-                       nblocks, dA, dB, dC);
+    hipLaunchKernelGGL((kron_grad_reduce_kernel<float, float, 16>), dim3(3 * 16 * 16), dim3(kGradBlock), 0, stream,
+                       part, nblocks, dA, dB, dC);
   }
   return 0;
 }

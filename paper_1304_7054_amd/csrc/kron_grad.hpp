@@ -481,27 +481,36 @@ __global__ __launch_bounds__(kGradBlock) __attribute__((amdgpu_waves_per_eu(2)))
   }
 }
 
-// dM(i, j) = sum over wavefronts (in order) and over the Q diagonal blocks of
-// the partial tiles (logical index q*n + i sits in slot slot_of(q*n + i)); one thread per entry of each requested factor; sums in
-// double.  Output column-major (i + n*j).
+// dM(i, j) = sum over the partial tiles and over the Q diagonal blocks of
+// each (logical index q*n + i sits in slot slot_of(q*n + i)).  One workgroup
+// per entry (i, j) of each factor: thread t sums partials t, t + 256, ... in
+// order in FP64, then a fixed-shape tree over the 256 thread sums finishes
+// the entry, so the result does not depend on timing.  Output column-major
+// (i + n*j).
 template <typename io_t, typename T, int N>
-__global__ __launch_bounds__(kGradBlock) void kron_grad_reduce_kernel(const T* __restrict__ ws, int64_t nwaves,
+__global__ __launch_bounds__(kGradBlock) void kron_grad_reduce_kernel(const T* __restrict__ ws, int64_t nparts,
                                                                       io_t* __restrict__ dA, io_t* __restrict__ dB,
                                                                       io_t* __restrict__ dC) {
   constexpr int Q = Geo<N>::Q;
-  const int f = blockIdx.x;
+  const int f = blockIdx.x / (N * N), e = blockIdx.x % (N * N);
   io_t* out = f == 0 ? dA : f == 1 ? dB : dC;
   if (out == nullptr) return;
-  for (int e = threadIdx.x; e < N * N; e += kGradBlock) {
-    const int i = e % N, j = e / N;
-    double s = 0.0;
-    for (int64_t w = 0; w < nwaves; ++w) {
-      const T* tile = ws + (w * 3 + f) * 256;
+  const int i = e % N, j = e / N;
+  double s = 0.0;
+  for (int64_t w = threadIdx.x; w < nparts; w += kGradBlock) {
+    const T* tile = ws + (w * 3 + f) * 256;
 #pragma unroll
-      for (int q = 0; q < Q; ++q) s += (double)tile[slot_of<N>(q * N + i) * 16 + slot_of<N>(q * N + j)];
-    }
-    out[i + N * j] = (io_t)s;
+    for (int q = 0; q < Q; ++q) s += (double)tile[slot_of<N>(q * N + i) * 16 + slot_of<N>(q * N + j)];
   }
+  __shared__ double red[kGradBlock];
+  red[threadIdx.x] = s;
+  __syncthreads();
+#pragma unroll
+  for (int h = kGradBlock / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[i + N * j] = (io_t)red[0];
 }
 
 }  // namespace kron
