@@ -46,6 +46,11 @@ class Oracle:
         lib.oracle_kron2d_grad_f64.restype = None
         lib.oracle_kron3d_grad_f64.argtypes = [ctypes.c_int, p, p, p, p, p, p, p, p, p, i64]
         lib.oracle_kron3d_grad_f64.restype = None
+        d, ch = ctypes.c_double, ctypes.c_char
+        lib.oracle_kron2d_ex_f64.argtypes = [ctypes.c_int, ch, ch, d, p, p, p, d, p, i64]
+        lib.oracle_kron2d_ex_f64.restype = None
+        lib.oracle_kron3d_ex_f64.argtypes = [ctypes.c_int, ch, ch, ch, d, p, p, p, p, d, p, i64]
+        lib.oracle_kron3d_ex_f64.restype = None
         lib.oracle_num_threads.argtypes = []
         lib.oracle_num_threads.restype = ctypes.c_int
         self.lib = lib
@@ -94,6 +99,28 @@ class Oracle:
         self.lib.oracle_kron3d_grad_f64(n, _ptr(A), _ptr(B), _ptr(C), _ptr(X), _ptr(dY),
                                         _ptr(dX), _ptr(dA), _ptr(dB), _ptr(dC), batch)
         return dX, dA, dB, dC
+
+    def kron2d_ex(self, n, opA, opB, alpha, A, B, X, beta, Y, batch):
+        """Y_p <- alpha * op(B) X_p op(A)^T + beta * Y_p (op 'N' or 'T'; Y not
+        read when beta == 0), in FP64; returns the new Y (a copy)."""
+        dt = np.float64
+        A, B = _prep(A, dt, n * n), _prep(B, dt, n * n)
+        X = _prep(X, dt, batch * n * n)
+        Y = np.array(_prep(Y, dt, batch * n * n), copy=True)
+        self.lib.oracle_kron2d_ex_f64(n, opA.encode(), opB.encode(), alpha, _ptr(A), _ptr(B), _ptr(X), beta,
+                                      _ptr(Y), batch)
+        return Y
+
+    def kron3d_ex(self, n, opA, opB, opC, alpha, A, B, C, X, beta, Y, batch):
+        """vec(Y_p) <- alpha * (op(A) kron op(B) kron op(C)) vec(X_p) + beta * vec(Y_p),
+        in FP64; returns the new Y (a copy)."""
+        dt = np.float64
+        A, B, C = (_prep(M, dt, n * n) for M in (A, B, C))
+        X = _prep(X, dt, batch * n ** 3)
+        Y = np.array(_prep(Y, dt, batch * n ** 3), copy=True)
+        self.lib.oracle_kron3d_ex_f64(n, opA.encode(), opB.encode(), opC.encode(), alpha, _ptr(A), _ptr(B),
+                                      _ptr(C), _ptr(X), beta, _ptr(Y), batch)
+        return Y
 
     def num_threads(self):
         """OpenMP threads the oracle uses."""
@@ -151,3 +178,11 @@ def kron3d_grad(*args, **kw):
 
 def num_threads():
     return default().num_threads()
+
+
+def kron2d_ex(*args, **kw):
+    return default().kron2d_ex(*args, **kw)
+
+
+def kron3d_ex(*args, **kw):
+    return default().kron3d_ex(*args, **kw)

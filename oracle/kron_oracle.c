@@ -125,6 +125,50 @@ DEFINE_KPQR(kpqr_f32, float)
 DEFINE_KRON3D(oracle_kron3d_f64, kpqr_f64, double)
 DEFINE_KRON3D(oracle_kron3d_f32, kpqr_f32, float)
 
+/* ---- Section 3's interface on the same storage (double only) ---------------
+ *   Y_p <- alpha * K(op(A), op(B)[, op(C)]) X_p + beta * Y_p,
+ *   op(M) = M for 'N' (or 'n') and M^T for 'T' (or 't').
+ * As in BLAS, beta == 0 means Y is not read (its old contents, even NaN, do
+ * not matter).  Written out plainly: the op matrices are formed explicitly,
+ * the action is taken with the functions above into a temporary, and the
+ * alpha/beta update is applied element by element. */
+
+static void op_matrix(int n, char op, const double* M, double* out) {
+  const int t = (op == 'T' || op == 't');
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < n; ++i) out[i + n * j] = t ? M[j + n * i] : M[i + n * j];
+}
+
+static void axpby(double alpha, const double* z, double beta, double* y, int64_t count) {
+  for (int64_t e = 0; e < count; ++e) y[e] = beta == 0.0 ? alpha * z[e] : alpha * z[e] + beta * y[e];
+}
+
+ORACLE_API void oracle_kron2d_ex_f64(int n, char opA, char opB, double alpha, const double* A, const double* B,
+                                     const double* X, double beta, double* Y, int64_t batch) {
+  double Ao[256], Bo[256];
+  op_matrix(n, opA, A, Ao);
+  op_matrix(n, opB, B, Bo);
+  const int64_t count = batch * n * n;
+  double* z = (double*)calloc(count ? count : 1, sizeof(double));
+  oracle_kron2d_f64(n, Ao, Bo, X, z, batch);
+  axpby(alpha, z, beta, Y, count);
+  free(z);
+}
+
+ORACLE_API void oracle_kron3d_ex_f64(int n, char opA, char opB, char opC, double alpha, const double* A,
+                                     const double* B, const double* C, const double* X, double beta, double* Y,
+                                     int64_t batch) {
+  double Ao[256], Bo[256], Co[256];
+  op_matrix(n, opA, A, Ao);
+  op_matrix(n, opB, B, Bo);
+  op_matrix(n, opC, C, Co);
+  const int64_t count = batch * n * n * n;
+  double* z = (double*)calloc(count ? count : 1, sizeof(double));
+  oracle_kron3d_f64(n, Ao, Bo, Co, X, z, batch);
+  axpby(alpha, z, beta, Y, count);
+  free(z);
+}
+
 /* ---- gradients (double only) ------------------------------------------ */
 
 static void transpose_n(int n, const double* M, double* Mt) {

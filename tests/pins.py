@@ -372,9 +372,38 @@ def pin_float_accuracy(orc, seed=13):
         assert 0 < e < 1e-6, ("f32 3-D accuracy", n, e)
 
 
+def pin_extended_interface(orc, seed=14):
+    """Y <- alpha * K(op(A), op(B)[, op(C)]) X + beta * Y against brute force
+    with the explicitly transposed factors (Section 3's interface), for every
+    op combination; beta = 0 must not read a NaN-filled Y."""
+    import itertools
+    rng = np.random.default_rng(seed)
+    for n, batch in ((3, 4), (2, 3)):
+        A, B, C = rand_mats(rng, n, 3)
+        opm = lambda M, o: mat(M, n).T if o == "T" else mat(M, n)
+        X2 = rng.standard_normal(batch * n * n)
+        Y2 = rng.standard_normal(batch * n * n)
+        for ops in itertools.product("NT", repeat=2):
+            K = np.kron(opm(A, ops[0]), opm(B, ops[1]))
+            base = (X2.reshape(batch, n * n) @ K.T).reshape(-1)
+            for alpha, beta in ((1.0, 0.0), (-0.5, 2.0)):
+                got = orc.kron2d_ex(n, ops[0], ops[1], alpha, A, B, X2, beta, Y2, batch)
+                assert rel(got, alpha * base + beta * Y2) < 1e-13, ("2d", ops, alpha, beta)
+        X3 = rng.standard_normal(batch * n ** 3)
+        Y3 = rng.standard_normal(batch * n ** 3)
+        for ops in itertools.product("NT", repeat=3):
+            K = np.kron(opm(A, ops[0]), np.kron(opm(B, ops[1]), opm(C, ops[2])))
+            base = (X3.reshape(batch, n ** 3) @ K.T).reshape(-1)
+            for alpha, beta in ((1.0, 0.0), (1.5, -0.25)):
+                got = orc.kron3d_ex(n, *ops, alpha, A, B, C, X3, beta, Y3, batch)
+                assert rel(got, alpha * base + beta * Y3) < 1e-13, ("3d", ops, alpha, beta)
+        got = orc.kron3d_ex(n, "T", "N", "T", 2.0, A, B, C, X3, 0.0, np.full(batch * n ** 3, np.nan), batch)
+        assert np.all(np.isfinite(got)), "beta = 0 read Y"
+
+
 ALL_PINS = [
     pin_worked_examples, pin_brute_force, pin_identity, pin_permutation,
     pin_small_integers, pin_mixed_product, pin_adjoint, pin_single_factor,
     pin_rank_one, pin_algorithm1, pin_linearity, pin_batch_independence,
-    pin_gradients, pin_float_accuracy,
+    pin_gradients, pin_float_accuracy, pin_extended_interface,
 ]

@@ -37,6 +37,13 @@ MUTATIONS = {
     "grad3d_U_factors": ("kpqr_f64(n, C, B, I, x, u, w1, w2);", "kpqr_f64(n, B, C, I, x, u, w1, w2);"),
     "grad3d_dB_index": ("dB[j + n * b] += s;", "dB[b + n * j] += s;"),
     "grad3d_dC_contraction": ("u[i * nn + j * n + c];", "u[i * nn + c * n + j];"),
+    "ex_transpose_ignored": ("const int t = (op == 'T' || op == 't');", "const int t = 0;"),
+    "ex_alpha_dropped": ("y[e] = beta == 0.0 ? alpha * z[e] : alpha * z[e] + beta * y[e];",
+                         "y[e] = beta == 0.0 ? z[e] : z[e] + beta * y[e];"),
+    "ex_beta_zero_reads_y": ("y[e] = beta == 0.0 ? alpha * z[e] : alpha * z[e] + beta * y[e];",
+                             "y[e] = alpha * z[e] + beta * y[e];"),
+    "ex_ops_swapped": ("  op_matrix(n, opA, A, Ao);\n  op_matrix(n, opB, B, Bo);\n  op_matrix(n, opC, C, Co);",
+                       "  op_matrix(n, opB, A, Ao);\n  op_matrix(n, opA, B, Bo);\n  op_matrix(n, opC, C, Co);"),
     "f32_accumulates_in_double": ("DEFINE_KRON2D(oracle_kron2d_f32, float)", "DEFINE_KRON2D(oracle_kron2d_f32_unused, float)\nORACLE_API void oracle_kron2d_f32(int n, const float* A, const float* B, const float* X, float* Y, int64_t batch) { (void)A; (void)B; for (int64_t i = 0; i < batch * n * n; ++i) Y[i] = X[i]; }"),
 }
 
