@@ -205,6 +205,38 @@ def measure_grouped(torch, steps, warmup):
             "sampled_max_rel_err": worst}
 
 
+def measure_ex(torch, steps, warmup):
+    """Section 3's interface on the 3-D n=16 FP32 workload: alpha = -1.5 and
+    op = (T, N, T), beta = 0 (per-call factor preparation included)."""
+    import paper_1304_7054_amd as kron
+    import workloads
+    n, batch = 16, workloads.BATCH_3D[16]
+    mats, X, Y = make_inputs(torch, 3, n, batch, "f32", 5)
+    ws = torch.empty(kron.kron_ex_workspace_size(3, n, kron.MODE_F32), dtype=torch.uint8, device="cuda")
+    fn = lambda stream=None: kron.kron3d_batched_ex_f32(n, "T", "N", "T", -1.5, *mats, X, 0.0, Y, batch, ws, stream)
+    wall, kmean, kmin = time_launches(torch, fn, (), max(10, steps // 2), warmup)
+    torch.cuda.synchronize()
+    import oracle
+    rng = np.random.default_rng(5)
+    hm = [m.double().cpu().numpy() for m in mats]
+    e, num, den = n ** 3, 0.0, 0.0
+    for q in rng.integers(0, batch, 16):
+        x = X[q * e:(q + 1) * e].double().cpu().numpy()
+        want = oracle.kron3d_ex(n, "T", "N", "T", -1.5, *hm, x, 0.0, np.zeros(e), 1)
+        got = Y[q * e:(q + 1) * e].double().cpu().numpy()
+        num += float(np.sum((got - want) ** 2))
+        den += float(np.sum(want ** 2))
+    alg = 2 * X.numel() * 4
+    del mats, X, Y, ws
+    torch.cuda.empty_cache()
+    return {"mode": "f32 extended 3-D n=16 (alpha=-1.5, ops T,N,T, beta=0)", "batch": batch,
+            "ms": round(kmean, 4), "ms_min": round(kmin, 4), "wall_ms_per_step": round(wall, 4),
+            "gflops": round(batch * flops_per_op(3, n) / (kmean * 1e-3) / 1e9, 1),
+            "gbs": round(alg / (kmean * 1e-3) / 1e9, 1),
+            "hbm_frac": round(alg / (kmean * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "alg_bytes": alg,
+            "sampled_rel_err": float(np.sqrt(num / den))}
+
+
 def measure_backward(torch, steps, warmup):
     """dX + dA + dB + dC of the 3-D n=16 FP32 workload (reads X and dY,
     writes dX: three 1 GiB streams)."""
@@ -474,6 +506,8 @@ def main():
             print(f"# measured {mode} {dim}-D n={n}: {others[-1]['gflops']} GFLOP/s", file=sys.stderr, flush=True)
         others.append(measure_grouped(torch, max(10, args.steps // 2), args.warmup))
         print(f"# measured grouped mixed: {others[-1]['gflops']} GFLOP/s", file=sys.stderr, flush=True)
+        others.append(measure_ex(torch, args.steps, args.warmup))
+        print(f"# measured extended interface: {others[-1]['gflops']} GFLOP/s", file=sys.stderr, flush=True)
         others.append(measure_backward(torch, args.steps, args.warmup))
         print(f"# measured backward: {others[-1]['ms']} ms", file=sys.stderr, flush=True)
 

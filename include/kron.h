@@ -160,6 +160,36 @@ int kron_graph_capture_grouped(const void* ws, void** graph_exec);
 int kron_graph_launch(void* graph_exec, hipStream_t stream);
 int kron_graph_destroy(void* graph_exec);
 
+/* ---- Section 3's interface: per-factor op and alpha ---------------------------- */
+
+/* Y_p <- alpha * K(op(A), op(B)[, op(C)]) X_p with op(M) = M ('N' or 'n') or
+   M^T ('T' or 't'), on the same storage and kernels as the plain entry points
+   (2-D: Y_p = alpha * op(B) X_p op(A)^T; 3-D: vec(Y_p) = alpha * (op(A) (x)
+   op(B) (x) op(C)) vec(X_p)).  Following the paper's transpose-once remark
+   (Section 2.2), op and alpha are applied once to the n x n factors, written
+   to the caller's workspace `ws` (device memory aligned to the element size,
+   at least kron_ex_workspace_size(dim, n, mode) bytes, mode KRON_MODE_F32 or
+   KRON_MODE_F64; owned by the caller), and the forward kernels
+   then run on those factors: the batch costs the same as the plain call.
+   beta is the BLAS output scale; this version supports beta == 0 only (Y is
+   written, never read) and returns -k for its position otherwise.  Returns 0
+   or -k (argument k invalid; a bad op character counts as invalid);
+   batch == 0 is a no-op.  Asynchronous on `stream`; `ws` must stay valid
+   until the call's kernels have run. */
+size_t kron_ex_workspace_size(int dim, int n, int mode);
+int kron2d_batched_ex_f32(int n, char opA, char opB, float alpha, const float* A, const float* B,
+                          const float* X, float beta, float* Y, int64_t batch, void* ws, size_t ws_bytes,
+                          hipStream_t stream);
+int kron2d_batched_ex_f64(int n, char opA, char opB, double alpha, const double* A, const double* B,
+                          const double* X, double beta, double* Y, int64_t batch, void* ws, size_t ws_bytes,
+                          hipStream_t stream);
+int kron3d_batched_ex_f32(int n, char opA, char opB, char opC, float alpha, const float* A, const float* B,
+                          const float* C, const float* X, float beta, float* Y, int64_t batch, void* ws,
+                          size_t ws_bytes, hipStream_t stream);
+int kron3d_batched_ex_f64(int n, char opA, char opB, char opC, double alpha, const double* A, const double* B,
+                          const double* C, const double* X, double beta, double* Y, int64_t batch, void* ws,
+                          size_t ws_bytes, hipStream_t stream);
+
 /* ---- backward ---------------------------------------------------------------- */
 
 /* Gradients of L = sum_p <dY_p, Y_p> for the forward actions above (the

@@ -17,6 +17,11 @@ from ._binding import (  # noqa: F401
     kron3d_backward_f32,
     kron3d_backward_f64,
     kron_backward_workspace_size,
+    kron2d_batched_ex_f32,
+    kron2d_batched_ex_f64,
+    kron3d_batched_ex_f32,
+    kron3d_batched_ex_f64,
+    kron_ex_workspace_size,
     kron2d_batched_adjoint_f32,
     kron2d_batched_adjoint_f64,
     kron2d_batched_bf16,

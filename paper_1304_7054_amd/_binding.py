@@ -36,7 +36,8 @@ class KronGroup(ctypes.Structure):
                 ("C", ctypes.c_void_p), ("X", ctypes.c_void_p), ("Y", ctypes.c_void_p),
                 ("count", ctypes.c_int64)]
 
-# (name, argument kinds); 'i' int, 'l' int64, 'p' pointer, 'S' stream, 'z' size_t
+# (name, argument kinds); 'i' int, 'l' int64, 'p' pointer, 'S' stream, 'z' size_t,
+# 'c' char, 'f' float, 'd' double
 SIGNATURES = {
     "kron2d_batched_f32": "ipppplS",
     "kron2d_batched_f64": "ipppplS",
@@ -54,10 +55,14 @@ SIGNATURES = {
     "kron3d_backward_f32": "ippppppppplpzS",
     "kron2d_backward_f64": "ippppppplpzS",
     "kron3d_backward_f64": "ippppppppplpzS",
+    "kron2d_batched_ex_f32": "iccfpppfplpzS",
+    "kron2d_batched_ex_f64": "iccdpppdplpzS",
+    "kron3d_batched_ex_f32": "icccfppppfplpzS",
+    "kron3d_batched_ex_f64": "icccdppppdplpzS",
 }
 
 _CT = {"i": ctypes.c_int, "l": ctypes.c_int64, "p": ctypes.c_void_p, "S": ctypes.c_void_p,
-       "z": ctypes.c_size_t}
+       "z": ctypes.c_size_t, "c": ctypes.c_char, "f": ctypes.c_float, "d": ctypes.c_double}
 
 
 def lib():
@@ -78,6 +83,8 @@ def lib():
         L.kron_version.restype = ctypes.c_char_p
         L.kron_backward_workspace_size.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int]
         L.kron_backward_workspace_size.restype = ctypes.c_size_t
+        L.kron_ex_workspace_size.argtypes = [ctypes.c_int] * 3
+        L.kron_ex_workspace_size.restype = ctypes.c_size_t
         L.kron_grouped_workspace_size.argtypes = [ctypes.POINTER(KronGroup), ctypes.c_int]
         L.kron_grouped_workspace_size.restype = ctypes.c_size_t
         L.kron_grouped_prepare.argtypes = [ctypes.POINTER(KronGroup), ctypes.c_int, ctypes.c_void_p,
@@ -268,6 +275,59 @@ def kron2d_backward_f64(n, A, B, X, dY, dX, dA, dB, batch, ws=None, stream=None)
 def kron3d_backward_f64(n, A, B, C, X, dY, dX, dA, dB, dC, batch, ws=None, stream=None):
     return _backward_call("kron3d_backward_f64", 3, torch.float64, MODE_F64, n, (A, B, C), X, dY, dX,
                           (dA, dB, dC), batch, ws, stream)
+
+
+def kron_ex_workspace_size(dim, n, mode):
+    """Bytes of workspace the extended entry points need (0 for invalid arguments)."""
+    return int(lib().kron_ex_workspace_size(int(dim), int(n), int(mode)))
+
+
+def _op_char(op, what):
+    if op not in ("N", "n", "T", "t"):
+        raise ValueError(f"{what} must be 'N' or 'T', got {op!r}")
+    return op.encode()
+
+
+def _ex_call(name, dim, dtype, mode, n, ops, alpha, mats, X, beta, Y, batch, ws, stream):
+    n, batch = int(n), int(batch)
+    if not 1 <= n <= 16:
+        raise ValueError(f"n must be in 1..16, got {n}")
+    if batch < 0:
+        raise ValueError("batch must be >= 0")
+    opc = [_op_char(op, f"op{i}") for i, op in enumerate(ops)]
+    ptrs = [_arr(M, dtype, n * n, f"factor {i}") for i, M in enumerate(mats)]
+    size = batch * n ** dim
+    px = _arr(X, dtype, size, "X")
+    py = _arr(Y, dtype, size, "Y")
+    if X.data_ptr() == Y.data_ptr() and size > 0:
+        raise ValueError("X and Y must not overlap")
+    need = kron_ex_workspace_size(dim, n, mode)
+    if ws is None:
+        ws = torch.empty(need, dtype=torch.uint8, device=X.device)
+    pw = _arr(ws, torch.uint8, need, "workspace")
+    return _call(name, n, *opc, alpha, *ptrs, px, beta, py, batch, pw, ws.numel(), _stream(stream))
+
+
+def kron2d_batched_ex_f32(n, opA, opB, alpha, A, B, X, beta, Y, batch, ws=None, stream=None):
+    """Y_p = alpha op(B) X_p op(A)^T, FP32 (beta must be 0; see include/kron.h)."""
+    return _ex_call("kron2d_batched_ex_f32", 2, torch.float32, MODE_F32, n, (opA, opB), float(alpha), (A, B), X,
+                    float(beta), Y, batch, ws, stream)
+
+
+def kron2d_batched_ex_f64(n, opA, opB, alpha, A, B, X, beta, Y, batch, ws=None, stream=None):
+    return _ex_call("kron2d_batched_ex_f64", 2, torch.float64, MODE_F64, n, (opA, opB), float(alpha), (A, B), X,
+                    float(beta), Y, batch, ws, stream)
+
+
+def kron3d_batched_ex_f32(n, opA, opB, opC, alpha, A, B, C, X, beta, Y, batch, ws=None, stream=None):
+    """vec(Y_p) = alpha (op(A) kron op(B) kron op(C)) vec(X_p), FP32 (beta must be 0)."""
+    return _ex_call("kron3d_batched_ex_f32", 3, torch.float32, MODE_F32, n, (opA, opB, opC), float(alpha),
+                    (A, B, C), X, float(beta), Y, batch, ws, stream)
+
+
+def kron3d_batched_ex_f64(n, opA, opB, opC, alpha, A, B, C, X, beta, Y, batch, ws=None, stream=None):
+    return _ex_call("kron3d_batched_ex_f64", 3, torch.float64, MODE_F64, n, (opA, opB, opC), float(alpha),
+                    (A, B, C), X, float(beta), Y, batch, ws, stream)
 
 
 def _groups_array(groups):

@@ -132,6 +132,58 @@ int check3d(int n, const void* A, const void* B, const void* C, const void* X, c
   return 0;
 }
 
+// op(M) per factor and alpha on the first factor, written once to `out`
+// (factor f at out + f * n^2, column-major).
+template <typename T>
+__global__ __launch_bounds__(256) void kron_prepare_factors_kernel(int n, int nf, const T* __restrict__ A,
+                                                                   const T* __restrict__ B, const T* __restrict__ C,
+                                                                   unsigned tmask, T alpha, T* __restrict__ out) {
+  const int nn = n * n;
+  for (int e = threadIdx.x; e < nf * nn; e += blockDim.x) {
+    const int f = e / nn, idx = e % nn, i = idx % n, j = idx / n;
+    const T* M = f == 0 ? A : f == 1 ? B : C;
+    const T v = ((tmask >> f) & 1u) ? M[j + n * i] : M[i + n * j];
+    out[e] = f == 0 ? alpha * v : v;
+  }
+}
+
+// 0 for 'N'/'n', 1 for 'T'/'t', -1 otherwise
+int op_bit(char op) { return (op == 'N' || op == 'n') ? 0 : (op == 'T' || op == 't') ? 1 : -1; }
+
+// Checks and factor preparation shared by the extended entry points (positions
+// follow their C signatures: n, the ops, alpha, the factors, X, beta, Y,
+// batch, ws, ws_bytes).  Returns 0, with the prepared factors being written
+// to ws on `stream`, or -k.
+template <typename T>
+int prepare_ex(int dim, int n, const char* ops, T alpha, const T* const* mats, const T* X, T beta, const T* Y,
+               int64_t batch, void* ws, size_t ws_bytes, hipStream_t stream, bool* skip) {
+  *skip = false;
+  if (n < 1 || n > KRON_MAX_N) return -1;
+  unsigned tmask = 0;
+  for (int f = 0; f < dim; ++f) {
+    const int b = op_bit(ops[f]);
+    if (b < 0) return -(2 + f);
+    tmask |= (unsigned)b << f;
+  }
+  const int kA = 2 + dim + 1;  // position of A (after n, the ops and alpha)
+  for (int f = 0; f < dim; ++f)
+    if (!mats[f]) return -(kA + f);
+  const int kX = kA + dim;
+  if (!X) return -kX;
+  if (beta != T(0)) return -(kX + 1);
+  if (!Y || (const void*)Y == (const void*)X) return -(kX + 2);
+  if (batch < 0) return -(kX + 3);
+  if (batch == 0) {
+    *skip = true;
+    return 0;
+  }
+  if (!ws || reinterpret_cast<uintptr_t>(ws) % sizeof(T) != 0) return -(kX + 4);
+  if (ws_bytes < (size_t)dim * n * n * sizeof(T)) return -(kX + 5);
+  hipLaunchKernelGGL(kron_prepare_factors_kernel<T>, dim3(1), dim3(256), 0, stream, n, dim, mats[0], mats[1],
+                     dim == 3 ? mats[2] : mats[1], tmask, alpha, static_cast<T*>(ws));
+  return 0;
+}
+
 }  // namespace
 
 namespace {
@@ -359,6 +411,59 @@ int kron_graph_destroy(void* graph_exec) {
   if (!graph_exec) return -1;
   hipError_t e = hipGraphExecDestroy(static_cast<hipGraphExec_t>(graph_exec));
   return e == hipSuccess ? 0 : (int)e;
+}
+
+size_t kron_ex_workspace_size(int dim, int n, int mode) {
+  if ((dim != 2 && dim != 3) || n < 1 || n > KRON_MAX_N) return 0;
+  if (mode != KRON_MODE_F32 && mode != KRON_MODE_F64) return 0;
+  return (size_t)dim * n * n * (mode == KRON_MODE_F64 ? 8 : 4);
+}
+
+int kron2d_batched_ex_f32(int n, char opA, char opB, float alpha, const float* A, const float* B, const float* X,
+                          float beta, float* Y, int64_t batch, void* ws, size_t ws_bytes, hipStream_t stream) {
+  const char ops[2] = {opA, opB};
+  const float* mats[2] = {A, B};
+  bool skip;
+  if (int rc = prepare_ex<float>(2, n, ops, alpha, mats, X, beta, Y, batch, ws, ws_bytes, stream, &skip)) return rc;
+  if (skip) return 0;
+  const float* P = static_cast<const float*>(ws);
+  return finish_launch(kron::fwd2d_f32(n, P, P + n * n, X, Y, batch, stream, false));
+}
+
+int kron2d_batched_ex_f64(int n, char opA, char opB, double alpha, const double* A, const double* B,
+                          const double* X, double beta, double* Y, int64_t batch, void* ws, size_t ws_bytes,
+                          hipStream_t stream) {
+  const char ops[2] = {opA, opB};
+  const double* mats[2] = {A, B};
+  bool skip;
+  if (int rc = prepare_ex<double>(2, n, ops, alpha, mats, X, beta, Y, batch, ws, ws_bytes, stream, &skip)) return rc;
+  if (skip) return 0;
+  const double* P = static_cast<const double*>(ws);
+  return finish_launch(kron::fwd2d_f64(n, P, P + n * n, X, Y, batch, stream, false));
+}
+
+int kron3d_batched_ex_f32(int n, char opA, char opB, char opC, float alpha, const float* A, const float* B,
+                          const float* C, const float* X, float beta, float* Y, int64_t batch, void* ws,
+                          size_t ws_bytes, hipStream_t stream) {
+  const char ops[3] = {opA, opB, opC};
+  const float* mats[3] = {A, B, C};
+  bool skip;
+  if (int rc = prepare_ex<float>(3, n, ops, alpha, mats, X, beta, Y, batch, ws, ws_bytes, stream, &skip)) return rc;
+  if (skip) return 0;
+  const float* P = static_cast<const float*>(ws);
+  return finish_launch(kron::fwd3d_f32(n, P, P + n * n, P + 2 * n * n, X, Y, batch, stream, false));
+}
+
+int kron3d_batched_ex_f64(int n, char opA, char opB, char opC, double alpha, const double* A, const double* B,
+                          const double* C, const double* X, double beta, double* Y, int64_t batch, void* ws,
+                          size_t ws_bytes, hipStream_t stream) {
+  const char ops[3] = {opA, opB, opC};
+  const double* mats[3] = {A, B, C};
+  bool skip;
+  if (int rc = prepare_ex<double>(3, n, ops, alpha, mats, X, beta, Y, batch, ws, ws_bytes, stream, &skip)) return rc;
+  if (skip) return 0;
+  const double* P = static_cast<const double*>(ws);
+  return finish_launch(kron::fwd3d_f64(n, P, P + n * n, P + 2 * n * n, X, Y, batch, stream, false));
 }
 
 const char* kron_status_string(int status) {
