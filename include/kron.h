@@ -160,22 +160,26 @@ int kron_graph_capture_grouped(const void* ws, void** graph_exec);
 int kron_graph_launch(void* graph_exec, hipStream_t stream);
 int kron_graph_destroy(void* graph_exec);
 
-/* ---- Section 3's interface: per-factor op and alpha ---------------------------- */
+/* ---- Section 3's interface: per-factor op, alpha and beta ---------------------- */
 
-/* Y_p <- alpha * K(op(A), op(B)[, op(C)]) X_p with op(M) = M ('N' or 'n') or
-   M^T ('T' or 't'), on the same storage and kernels as the plain entry points
-   (2-D: Y_p = alpha * op(B) X_p op(A)^T; 3-D: vec(Y_p) = alpha * (op(A) (x)
-   op(B) (x) op(C)) vec(X_p)).  Following the paper's transpose-once remark
+/* Y_p <- alpha * K(op(A), op(B)[, op(C)]) X_p + beta * Y_p (Section 2.2's
+   batched update) with op(M) = M ('N' or 'n') or M^T ('T' or 't'), on the
+   same storage as the plain entry points (2-D: Y_p = alpha * op(B) X_p
+   op(A)^T + beta * Y_p; 3-D: vec(Y_p) = alpha * (op(A) (x) op(B) (x) op(C))
+   vec(X_p) + beta * vec(Y_p)).  Following the paper's transpose-once remark
    (Section 2.2), op and alpha are applied once to the n x n factors, written
    to the caller's workspace `ws` (device memory aligned to the element size,
    at least kron_ex_workspace_size(dim, n, mode) bytes, mode KRON_MODE_F32 or
-   KRON_MODE_F64; owned by the caller), and the forward kernels
-   then run on those factors: the batch costs the same as the plain call.
-   beta is the BLAS output scale; this version supports beta == 0 only (Y is
-   written, never read) and returns -k for its position otherwise.  Returns 0
-   or -k (argument k invalid; a bad op character counts as invalid);
-   batch == 0 is a no-op.  Asynchronous on `stream`; `ws` must stay valid
-   until the call's kernels have run. */
+   KRON_MODE_F64; owned by the caller).
+   beta == 0: Y is written and never read (NaN in Y does not propagate), and
+   the plain forward kernels run on the prepared factors, so the batch costs
+   the same as the plain call.
+   beta != 0: every output element is read once and updated in place by the
+   lane that computes it (one more pass over Y; NaN in Y propagates as in
+   BLAS).
+   Returns 0 or -k (argument k invalid; a bad op character counts as
+   invalid); batch == 0 is a no-op.  Asynchronous on `stream`; `ws` must stay
+   valid until the call's kernels have run. */
 size_t kron_ex_workspace_size(int dim, int n, int mode);
 int kron2d_batched_ex_f32(int n, char opA, char opB, float alpha, const float* A, const float* B,
                           const float* X, float beta, float* Y, int64_t batch, void* ws, size_t ws_bytes,

@@ -170,7 +170,6 @@ int prepare_ex(int dim, int n, const char* ops, T alpha, const T* const* mats, c
     if (!mats[f]) return -(kA + f);
   const int kX = kA + dim;
   if (!X) return -kX;
-  if (beta != T(0)) return -(kX + 1);
   if (!Y || (const void*)Y == (const void*)X) return -(kX + 2);
   if (batch < 0) return -(kX + 3);
   if (batch == 0) {
@@ -427,7 +426,8 @@ int kron2d_batched_ex_f32(int n, char opA, char opB, float alpha, const float* A
   if (int rc = prepare_ex<float>(2, n, ops, alpha, mats, X, beta, Y, batch, ws, ws_bytes, stream, &skip)) return rc;
   if (skip) return 0;
   const float* P = static_cast<const float*>(ws);
-  return finish_launch(kron::fwd2d_f32(n, P, P + n * n, X, Y, batch, stream, false));
+  return finish_launch(beta != 0.0f ? kron::beta2d_f32(n, P, P + n * n, X, Y, batch, beta, stream)
+                                     : kron::fwd2d_f32(n, P, P + n * n, X, Y, batch, stream, false));
 }
 
 int kron2d_batched_ex_f64(int n, char opA, char opB, double alpha, const double* A, const double* B,
@@ -439,7 +439,8 @@ int kron2d_batched_ex_f64(int n, char opA, char opB, double alpha, const double*
   if (int rc = prepare_ex<double>(2, n, ops, alpha, mats, X, beta, Y, batch, ws, ws_bytes, stream, &skip)) return rc;
   if (skip) return 0;
   const double* P = static_cast<const double*>(ws);
-  return finish_launch(kron::fwd2d_f64(n, P, P + n * n, X, Y, batch, stream, false));
+  return finish_launch(beta != 0.0 ? kron::beta2d_f64(n, P, P + n * n, X, Y, batch, beta, stream)
+                                    : kron::fwd2d_f64(n, P, P + n * n, X, Y, batch, stream, false));
 }
 
 int kron3d_batched_ex_f32(int n, char opA, char opB, char opC, float alpha, const float* A, const float* B,
@@ -451,7 +452,8 @@ int kron3d_batched_ex_f32(int n, char opA, char opB, char opC, float alpha, cons
   if (int rc = prepare_ex<float>(3, n, ops, alpha, mats, X, beta, Y, batch, ws, ws_bytes, stream, &skip)) return rc;
   if (skip) return 0;
   const float* P = static_cast<const float*>(ws);
-  return finish_launch(kron::fwd3d_f32(n, P, P + n * n, P + 2 * n * n, X, Y, batch, stream, false));
+  return finish_launch(beta != 0.0f ? kron::beta3d_f32(n, P, P + n * n, P + 2 * n * n, X, Y, batch, beta, stream)
+                                     : kron::fwd3d_f32(n, P, P + n * n, P + 2 * n * n, X, Y, batch, stream, false));
 }
 
 int kron3d_batched_ex_f64(int n, char opA, char opB, char opC, double alpha, const double* A, const double* B,
@@ -463,7 +465,8 @@ int kron3d_batched_ex_f64(int n, char opA, char opB, char opC, double alpha, con
   if (int rc = prepare_ex<double>(3, n, ops, alpha, mats, X, beta, Y, batch, ws, ws_bytes, stream, &skip)) return rc;
   if (skip) return 0;
   const double* P = static_cast<const double*>(ws);
-  return finish_launch(kron::fwd3d_f64(n, P, P + n * n, P + 2 * n * n, X, Y, batch, stream, false));
+  return finish_launch(beta != 0.0 ? kron::beta3d_f64(n, P, P + n * n, P + 2 * n * n, X, Y, batch, beta, stream)
+                                    : kron::fwd3d_f64(n, P, P + n * n, P + 2 * n * n, X, Y, batch, stream, false));
 }
 
 const char* kron_status_string(int status) {

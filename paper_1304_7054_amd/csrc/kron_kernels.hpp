@@ -82,6 +82,25 @@ __device__ __forceinline__ bool all_finite(const V& v) {
   return __builtin_isfinite(v[0]) && __builtin_isfinite(v[1]) && __builtin_isfinite(v[2]) && __builtin_isfinite(v[3]);
 }
 
+// Output stores.  kBeta: the BLAS-style output update Y <- v + beta * Y of
+// Section 3's interface, reading the old value at the address it writes, in
+// the same lane, so the update needs no synchronisation.
+template <bool kBeta, typename io_t, typename V, typename S>
+__device__ __forceinline__ void put4(io_t* p, V v, S beta) {
+  if constexpr (kBeta) {
+    const V y = Mem<io_t>::load4(p);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) v[r] = v[r] + beta * y[r];
+  }
+  Mem<io_t>::store4(p, v);
+}
+
+template <bool kBeta, typename io_t, typename E, typename S>
+__device__ __forceinline__ void put1(io_t* p, E v, S beta) {
+  if constexpr (kBeta) v = v + beta * Mem<io_t>::load1(p);
+  Mem<io_t>::store1(p, v);
+}
+
 // Offset (elements, relative to the tile's first operand) and packed-operand
 // number contributed by one axis.  `stride` is the element stride of the axis
 // inside an operand (n^2, n or 1); `opmul` its packed-operand multiplier
@@ -161,17 +180,18 @@ struct Tile2D {
     return M::template da<kS>(fA, M::template da_in<kS>(fB, x));
   }
 
-  __device__ __forceinline__ void store(io_t* Yt, int64_t rem, const acc_t& y_in, int only = -1) const {
+  template <bool kBeta = false, typename S = float>
+  __device__ __forceinline__ void store(io_t* Yt, int64_t rem, const acc_t& y_in, int only = -1, S beta = S(0)) const {
     acc_t y = y_in;
     if constexpr (kRegroup) transpose_groups_regs(y);
     if constexpr (N == 16 && kStoreVec) {
-      Mem<io_t>::store4(Yt + pL.off + offO[0], y);
+      put4<kBeta>(Yt + pL.off + offO[0], y, beta);
     } else if constexpr (kStoreVec) {
-      if (pL.valid && vO[0] && take(pL.op + opO[0], rem, only)) Mem<io_t>::store4(Yt + pL.off + offO[0], y);
+      if (pL.valid && vO[0] && take(pL.op + opO[0], rem, only)) put4<kBeta>(Yt + pL.off + offO[0], y, beta);
     } else {
 #pragma unroll
       for (int r = 0; r < 4; ++r)
-        if (pL.valid && vO[r] && take(pL.op + opO[r], rem, only)) Mem<io_t>::store1(Yt + pL.off + offO[r], y[r]);
+        if (pL.valid && vO[r] && take(pL.op + opO[r], rem, only)) put1<kBeta>(Yt + pL.off + offO[r], y[r], beta);
     }
   }
 
@@ -179,15 +199,16 @@ struct Tile2D {
   // neighbours through the zero blocks of the factor tiles (0 * Inf = NaN).
   // When a tile's result holds any non-finite value, it is redone one
   // operand at a time so that IEEE propagation stays inside each operand.
-  __device__ __forceinline__ void finish(const io_t* Xt, io_t* Yt, int64_t rem, const acc_t& y) const {
+  template <bool kBeta = false, typename S = float>
+  __device__ __forceinline__ void finish(const io_t* Xt, io_t* Yt, int64_t rem, const acc_t& y, S beta = S(0)) const {
     if constexpr (kOps > 1) {
       if (__any(!all_finite(y))) {
         const int last = rem < kOps ? (int)rem : kOps;
-        for (int o = 0; o < last; ++o) store(Yt, rem, compute(load(Xt, rem, o)), o);
+        for (int o = 0; o < last; ++o) store<kBeta>(Yt, rem, compute(load(Xt, rem, o)), o, beta);
         return;
       }
     }
-    store(Yt, rem, y);
+    store<kBeta>(Yt, rem, y, -1, beta);
   }
 };
 
@@ -328,29 +349,34 @@ struct Tile3D {
     stage3(t);
   }
 
-  __device__ __forceinline__ void store_slab(io_t* Yt, int64_t rem, int i, const acc_t& v, int only = -1) const {
+  template <bool kBeta = false, typename S = float>
+  __device__ __forceinline__ void store_slab(io_t* Yt, int64_t rem, int i, const acc_t& v, int only = -1,
+                                             S beta = S(0)) const {
     AxisPart<N, E> pS(i, N * N, Q * Q);  // slab on the slow axis
     if constexpr (N == 16 && kStoreVec) {
-      Mem<io_t>::store4(Yt + pS.off + pLo.off + offO[0], v);
+      put4<kBeta>(Yt + pS.off + pLo.off + offO[0], v, beta);
     } else if constexpr (kStoreVec) {
       if (pS.valid && pLo.valid && vO[0] && take(pS.op + pLo.op + opO[0], rem, only))
-        Mem<io_t>::store4(Yt + pS.off + pLo.off + offO[0], v);
+        put4<kBeta>(Yt + pS.off + pLo.off + offO[0], v, beta);
     } else {
 #pragma unroll
       for (int r = 0; r < 4; ++r)
         if (pS.valid && pLo.valid && vO[r] && take(pS.op + pLo.op + opO[r], rem, only))
-          Mem<io_t>::store1(Yt + pS.off + pLo.off + offO[r], v[r]);
+          put1<kBeta>(Yt + pS.off + pLo.off + offO[r], v[r], beta);
     }
   }
 
-  __device__ __forceinline__ void store(io_t* Yt, int64_t rem, const acc_t (&t)[16], int only = -1) const {
+  template <bool kBeta = false, typename S = float>
+  __device__ __forceinline__ void store(io_t* Yt, int64_t rem, const acc_t (&t)[16], int only = -1,
+                                        S beta = S(0)) const {
 #pragma unroll
-    for (int i = 0; i < 16; ++i) store_slab(Yt, rem, i, t[i], only);
+    for (int i = 0; i < 16; ++i) store_slab<kBeta>(Yt, rem, i, t[i], only, beta);
   }
 
   // Same isolation rule as the 2-D tile: a packed tile whose result holds a
   // non-finite value is recomputed one operand at a time.
-  __device__ __forceinline__ void finish(const io_t* Xt, io_t* Yt, int64_t rem, acc_t (&t)[16]) const {
+  template <bool kBeta = false, typename S = float>
+  __device__ __forceinline__ void finish(const io_t* Xt, io_t* Yt, int64_t rem, acc_t (&t)[16], S beta = S(0)) const {
     if constexpr (kOps > 1) {
       bool fin = true;
 #pragma unroll
@@ -360,12 +386,12 @@ struct Tile3D {
         for (int o = 0; o < last; ++o) {
           load(Xt, rem, t, o);
           compute(t);
-          store(Yt, rem, t, o);
+          store<kBeta>(Yt, rem, t, o, beta);
         }
         return;
       }
     }
-    store(Yt, rem, t);
+    store<kBeta>(Yt, rem, t, -1, beta);
   }
 };
 
@@ -486,6 +512,56 @@ __global__ __launch_bounds__(kBlock) void kron3d_kernel(const typename M::io_t* 
       tile.load(X + t * kStep, batch - t * T::kOps, v);
       tile.compute(v);
       tile.finish(X + t * kStep, Y + t * kStep, batch - t * T::kOps, v);
+    }
+  }
+}
+
+// Y_p <- K X_p + beta Y_p for beta != 0 (Section 3's output update; alpha is
+// folded into the factors by the caller).  The tile loops of the plain
+// kernels (2-D: four tiles in flight per wavefront; 3-D: contiguous 1 KiB
+// rows), with every lane reading the old output where it stores.  FP32 and
+// FP64 storage only (io_t is the arithmetic type).
+template <class M, int N, bool kVec, int kDim>
+__global__ __launch_bounds__(kBlock) void kron_beta_kernel(const typename M::io_t* __restrict__ A,
+                                                           const typename M::io_t* __restrict__ B,
+                                                           const typename M::io_t* __restrict__ C,
+                                                           const typename M::io_t* __restrict__ X,
+                                                           typename M::io_t* __restrict__ Y, int64_t batch,
+                                                           int64_t ntiles, typename M::io_t beta) {
+  using acc_t = typename M::acc_t;
+  const int l = threadIdx.x & 63, L = l & 15, g = l >> 4;
+  const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * kBlock) >> 6;
+  if constexpr (kDim == 2) {
+    using T = Tile2D<M, N, kVec, false>;
+    constexpr int kTiles = 4;
+    const T tile(A, B, L, g);
+    for (int64_t base = wave * kTiles; base < ntiles; base += nwaves * kTiles) {
+      acc_t x[kTiles];
+#pragma unroll
+      for (int j = 0; j < kTiles; ++j) {
+        const int64_t t = base + j;
+        if (t < ntiles) x[j] = tile.load(X + t * T::kOps * T::E, batch - t * T::kOps);
+        else x[j] = acc_t{0, 0, 0, 0};
+      }
+#pragma unroll
+      for (int j = 0; j < kTiles; ++j) x[j] = tile.compute(x[j]);
+#pragma unroll
+      for (int j = 0; j < kTiles; ++j) {
+        const int64_t t = base + j;
+        if (t < ntiles)
+          tile.template finish<true>(X + t * T::kOps * T::E, Y + t * T::kOps * T::E, batch - t * T::kOps, x[j], beta);
+      }
+    }
+  } else {
+    using T = Tile3D<M, N, kVec, false, true>;
+    constexpr int64_t kStep = (int64_t)T::kOps * T::E;
+    const T tile(A, B, C, L, g);
+    for (int64_t t = wave; t < ntiles; t += nwaves) {
+      acc_t v[16];
+      tile.load(X + t * kStep, batch - t * T::kOps, v);
+      tile.compute(v);
+      tile.template finish<true>(X + t * kStep, Y + t * kStep, batch - t * T::kOps, v, beta);
     }
   }
 }

@@ -187,6 +187,31 @@ int launch3d_n(const typename M::io_t* A, const typename M::io_t* B, const typen
   return 0;
 }
 
+// beta != 0 (kron_beta_kernel): the vector path when X and Y are aligned,
+// a persistent grid sized by occupancy.
+template <class M, int Dim, int N>
+int launch_beta_n(const typename M::io_t* A, const typename M::io_t* B, const typename M::io_t* C,
+                  const typename M::io_t* X, typename M::io_t* Y, int64_t batch, typename M::io_t beta,
+                  hipStream_t stream) {
+  using io_t = typename M::io_t;
+  constexpr int64_t Q = Geo<N>::Q;
+  constexpr int64_t ops = Dim == 2 ? Q * Q : Q * Q * Q;
+  const int64_t ntiles = (batch + ops - 1) / ops;
+  const int64_t waves = Dim == 2 ? (ntiles + 3) / 4 : ntiles;  // 2-D: four tiles per wavefront step
+  auto run = [&](auto k) {
+    hipLaunchKernelGGL(k, dim3(grid_blocks(waves, occupancy_blocks(k), 0)), dim3(kBlock), 0, stream, A, B, C, X, Y,
+                       batch, ntiles, beta);
+  };
+  if constexpr (Geo<N>::kVec) {
+    if (aligned_to(X, Mem<io_t>::kAlign) && aligned_to(Y, Mem<io_t>::kAlign)) {
+      run(kron_beta_kernel<M, N, true, Dim>);
+      return 0;
+    }
+  }
+  run(kron_beta_kernel<M, N, false, Dim>);
+  return 0;
+}
+
 #define KRON_N_CASES(F) \
   F(1) F(2) F(3) F(4) F(5) F(6) F(7) F(8) F(9) F(10) F(11) F(12) F(13) F(14) F(15) F(16)
 
@@ -197,6 +222,21 @@ int launch2d(int n, const typename M::io_t* A, const typename M::io_t* B, const 
 #define KRON_CASE(NN) \
   case NN:            \
     return launch2d_n<M, NN, kTrans>(A, B, X, Y, batch, stream, mode);
+    KRON_N_CASES(KRON_CASE)
+#undef KRON_CASE
+    default:
+      return -1;
+  }
+}
+
+template <class M, int Dim>
+int launch_beta(int n, const typename M::io_t* A, const typename M::io_t* B, const typename M::io_t* C,
+                const typename M::io_t* X, typename M::io_t* Y, int64_t batch, typename M::io_t beta,
+                hipStream_t stream) {
+  switch (n) {
+#define KRON_CASE(NN) \
+  case NN:            \
+    return launch_beta_n<M, Dim, NN>(A, B, C, X, Y, batch, beta, stream);
     KRON_N_CASES(KRON_CASE)
 #undef KRON_CASE
     default:

@@ -1,9 +1,10 @@
 """Parity of the extended entry points, Y <- alpha K(op(A), op(B)[, op(C)]) X
-(Section 3's batched interface with op in {N, T}; beta = 0), against the
++ beta Y (Section 3's batched interface with op in {N, T}), against the
 FP64 oracle's extended interface: every op combination, several n (tiled and
-staged paths, ragged batches), alpha values including 0 and negative ones,
-Y filled with NaN so that an unwritten or read output shows.  A non-zero
-beta, a bad op character and a short workspace are rejected with their
+staged paths, ragged batches), alpha values including 0 and negative ones.
+With beta = 0, Y starts as NaN so that an unwritten or read output shows;
+with beta != 0, Y starts as seeded values that the update must read.  A bad
+op character and a short or missing workspace are rejected with their
 argument's position."""
 import itertools
 
@@ -24,25 +25,34 @@ def _need_gpu():
         pytest.skip("no GPU")
 
 
-def _run(mode, dim, n, ops, alpha, batch, seed):
+def _run(mode, dim, n, ops, alpha, batch, seed, beta=0.0, offset=0):
     rng = np.random.default_rng(seed)
     mats = [rng.uniform(-1, 1, n * n) for _ in range(dim)]
     X = rng.standard_normal(batch * n ** dim)
+    Y0 = rng.standard_normal(batch * n ** dim)
     dt = DT[mode]
+    size = batch * n ** dim
     tm = [torch.tensor(m, dtype=dt, device="cuda") for m in mats]
-    tx = torch.tensor(X, dtype=dt, device="cuda")
-    ty = torch.full_like(tx, float("nan"))
+    # offset > 0: X and Y start `offset` elements into their allocations (unaligned arrays)
+    bx = torch.zeros(size + offset, dtype=dt, device="cuda")
+    by = torch.zeros(size + offset, dtype=dt, device="cuda")
+    tx, ty = bx[offset:], by[offset:]
+    tx.copy_(torch.tensor(X, dtype=dt))
+    if beta == 0.0:
+        ty.fill_(float("nan"))
+    else:
+        ty.copy_(torch.tensor(Y0, dtype=dt))
+    hy0 = ty.double().cpu().numpy()
     fn = getattr(kron, f"kron{dim}d_batched_ex_{mode}")
-    assert fn(n, *ops, alpha, *tm, tx, 0.0, ty, batch) == 0
+    assert fn(n, *ops, alpha, *tm, tx, beta, ty, batch) == 0
     torch.cuda.synchronize()
     got = ty.double().cpu().numpy()
     hm = [t.double().cpu().numpy() for t in tm]
     hx = tx.double().cpu().numpy()
-    nan = np.full(hx.size, np.nan)
     if dim == 2:
-        want = oracle.kron2d_ex(n, *ops, alpha, *hm, hx, 0.0, nan, batch)
+        want = oracle.kron2d_ex(n, *ops, alpha, *hm, hx, beta, hy0, batch)
     else:
-        want = oracle.kron3d_ex(n, *ops, alpha, *hm, hx, 0.0, nan, batch)
+        want = oracle.kron3d_ex(n, *ops, alpha, *hm, hx, beta, hy0, batch)
     assert np.all(np.isfinite(got))
     den = np.linalg.norm(want)
     err = np.linalg.norm(got - want) / den if den > 0 else np.linalg.norm(got)
@@ -70,6 +80,55 @@ def test_ex_alpha_values(alpha):
     _need_gpu()
     _run("f32", 3, 16, ("T", "n", "t"), alpha, 129, 5)
     _run("f64", 2, 12, ("n", "T"), alpha, 77, 6)
+
+
+@pytest.mark.parametrize("mode", ["f32", "f64"])
+@pytest.mark.parametrize("n", [1, 2, 4, 5, 7, 8, 10, 13, 16])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_ex_beta_nonzero(mode, n, dim):
+    """beta != 0: the update reads the old Y (every n: packed tiles, ragged
+    last tile)."""
+    _need_gpu()
+    batch = 301 if dim == 2 else 37
+    ops = ("T", "N", "T")[:dim]
+    _run(mode, dim, n, ops, -0.75, batch, 400 + n + dim, beta=1.25)
+
+
+@pytest.mark.parametrize("alpha,beta", [(0.0, 2.0), (1.0, -1.0), (2.5, 0.5)])
+def test_ex_beta_values(alpha, beta):
+    _need_gpu()
+    _run("f32", 3, 16, ("N", "T", "N"), alpha, 257, 9, beta=beta)
+    _run("f64", 2, 16, ("T", "T"), alpha, 1001, 10, beta=beta)
+
+
+@pytest.mark.parametrize("mode", ["f32", "f64"])
+def test_ex_beta_unaligned(mode):
+    """X and Y one element past a 16-byte boundary: the scalar store path."""
+    _need_gpu()
+    _run(mode, 3, 16, ("T", "T", "T"), 1.5, 9, 12, beta=-2.0, offset=1)
+    _run(mode, 2, 8, ("N", "T"), 1.5, 33, 13, beta=-2.0, offset=1)
+
+
+def test_ex_beta_isolates_nonfinite_operands():
+    """A NaN in one operand of a packed tile (n = 5: several operands per
+    tile) stays in that operand; the others match the oracle."""
+    _need_gpu()
+    n, batch = 5, 64
+    rng = np.random.default_rng(31)
+    mats = [rng.uniform(-1, 1, n * n) for _ in range(3)]
+    X = rng.standard_normal(batch * n ** 3)
+    X[7 * n ** 3 + 3] = np.nan
+    Y0 = rng.standard_normal(batch * n ** 3)
+    tm = [torch.tensor(m, dtype=torch.float64, device="cuda") for m in mats]
+    tx = torch.tensor(X, device="cuda")
+    ty = torch.tensor(Y0, device="cuda")
+    kron.kron3d_batched_ex_f64(n, "N", "T", "N", 1.0, *tm, tx, 0.5, ty, batch)
+    torch.cuda.synchronize()
+    got = ty.cpu().numpy().reshape(batch, -1)
+    want = oracle.kron3d_ex(n, "N", "T", "N", 1.0, *mats, X, 0.5, Y0, batch).reshape(batch, -1)
+    assert np.isnan(got[7]).any()
+    keep = np.arange(batch) != 7
+    np.testing.assert_allclose(got[keep], want[keep], rtol=1e-12, atol=1e-12)
 
 
 def test_ex_identity_ops_equal_plain_call():
@@ -103,12 +162,13 @@ def test_ex_rejections():
                                        wsp, wsb, s)
 
     assert call() == 0
+    assert call(beta=1.0) == 0
     assert call(opA=b"C") == -2           # op of A
-    assert call(beta=1.0) == -10          # beta (10th argument)
     assert call(wsp=0) == -13             # workspace
+    assert call(wsp=ws.data_ptr() + 2) == -13
     assert call(wsb=ws.numel() - 1) == -14
     torch.cuda.synchronize()
-    with pytest.raises(kron.KronError):
-        kron.kron3d_batched_ex_f32(n, "N", "N", "N", 1.0, *mats, X, 0.5, Y, batch)
+    with pytest.raises(ValueError):       # short workspace, caught by the binding
+        kron.kron3d_batched_ex_f32(n, "N", "N", "N", 1.0, *mats, X, 0.5, Y, batch, ws=ws[:8])
     with pytest.raises(ValueError):
         kron.kron2d_batched_ex_f32(n, "X", "N", 1.0, mats[0], mats[1], X, 0.0, Y, batch)
