@@ -47,7 +47,7 @@ class Oracle:
         lib.oracle_kron3d_grad_f64.argtypes = [ctypes.c_int, p, p, p, p, p, p, p, p, p, i64]
         lib.oracle_kron3d_grad_f64.restype = None
         d, ch = ctypes.c_double, ctypes.c_char
-        lib.oracle_kron2d_ex_f64.argtypes = [ctypes.c_int, ch, ch, d, p, p, p, d, p, i64]
+        lib.oracle_kron2d_ex_f64.argtypes = [ctypes.c_int, ch, ch, ch, d, p, p, p, d, p, i64]
         lib.oracle_kron2d_ex_f64.restype = None
         lib.oracle_kron3d_ex_f64.argtypes = [ctypes.c_int, ch, ch, ch, d, p, p, p, p, d, p, i64]
         lib.oracle_kron3d_ex_f64.restype = None
@@ -100,15 +100,15 @@ class Oracle:
                                         _ptr(dX), _ptr(dA), _ptr(dB), _ptr(dC), batch)
         return dX, dA, dB, dC
 
-    def kron2d_ex(self, n, opA, opB, alpha, A, B, X, beta, Y, batch):
-        """Y_p <- alpha * op(B) X_p op(A)^T + beta * Y_p (op 'N' or 'T'; Y not
-        read when beta == 0), in FP64; returns the new Y (a copy)."""
+    def kron2d_ex(self, n, opA, opB, alpha, A, B, X, beta, Y, batch, opX="N"):
+        """Y_p <- alpha * op(B) op(X_p) op(A)^T + beta * Y_p (op 'N' or 'T'; Y
+        not read when beta == 0), in FP64; returns the new Y (a copy)."""
         dt = np.float64
         A, B = _prep(A, dt, n * n), _prep(B, dt, n * n)
         X = _prep(X, dt, batch * n * n)
         Y = np.array(_prep(Y, dt, batch * n * n), copy=True)
-        self.lib.oracle_kron2d_ex_f64(n, opA.encode(), opB.encode(), alpha, _ptr(A), _ptr(B), _ptr(X), beta,
-                                      _ptr(Y), batch)
+        self.lib.oracle_kron2d_ex_f64(n, opA.encode(), opB.encode(), opX.encode(), alpha, _ptr(A), _ptr(B),
+                                      _ptr(X), beta, _ptr(Y), batch)
         return Y
 
     def kron3d_ex(self, n, opA, opB, opC, alpha, A, B, C, X, beta, Y, batch):

@@ -143,16 +143,22 @@ static void axpby(double alpha, const double* z, double beta, double* y, int64_t
   for (int64_t e = 0; e < count; ++e) y[e] = beta == 0.0 ? alpha * z[e] : alpha * z[e] + beta * y[e];
 }
 
-ORACLE_API void oracle_kron2d_ex_f64(int n, char opA, char opB, double alpha, const double* A, const double* B,
-                                     const double* X, double beta, double* Y, int64_t batch) {
+/* 2-D: Y_p <- alpha * K(op(A), op(B))(op(X_p)) + beta * Y_p.  Only in 2-D
+ * may op act on the operands too (Section 2.2); op(X_p) is formed
+ * explicitly, operand by operand, before the plain action. */
+ORACLE_API void oracle_kron2d_ex_f64(int n, char opA, char opB, char opX, double alpha, const double* A,
+                                     const double* B, const double* X, double beta, double* Y, int64_t batch) {
   double Ao[256], Bo[256];
   op_matrix(n, opA, A, Ao);
   op_matrix(n, opB, B, Bo);
-  const int64_t count = batch * n * n;
+  const int64_t nn = (int64_t)n * n, count = batch * nn;
+  double* xo = (double*)calloc(count ? count : 1, sizeof(double));
+  for (int64_t p = 0; p < batch; ++p) op_matrix(n, opX, X + p * nn, xo + p * nn);
   double* z = (double*)calloc(count ? count : 1, sizeof(double));
-  oracle_kron2d_f64(n, Ao, Bo, X, z, batch);
+  oracle_kron2d_f64(n, Ao, Bo, xo, z, batch);
   axpby(alpha, z, beta, Y, count);
   free(z);
+  free(xo);
 }
 
 ORACLE_API void oracle_kron3d_ex_f64(int n, char opA, char opB, char opC, double alpha, const double* A,

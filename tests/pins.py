@@ -375,7 +375,8 @@ def pin_float_accuracy(orc, seed=13):
 def pin_extended_interface(orc, seed=14):
     """Y <- alpha * K(op(A), op(B)[, op(C)]) X + beta * Y against brute force
     with the explicitly transposed factors (Section 3's interface), for every
-    op combination; beta = 0 must not read a NaN-filled Y."""
+    op combination, and in 2-D with op on the operands as well; beta = 0 must
+    not read a NaN-filled Y."""
     import itertools
     rng = np.random.default_rng(seed)
     for n, batch in ((3, 4), (2, 3)):
@@ -399,6 +400,14 @@ def pin_extended_interface(orc, seed=14):
                 assert rel(got, alpha * base + beta * Y3) < 1e-13, ("3d", ops, alpha, beta)
         got = orc.kron3d_ex(n, "T", "N", "T", 2.0, A, B, C, X3, 0.0, np.full(batch * n ** 3, np.nan), batch)
         assert np.all(np.isfinite(got)), "beta = 0 read Y"
+        # 2-D op on the operands: each X_p transposed explicitly (numpy index
+        # [p, m, l] holds X_p(l, m) of the column-major operand)
+        X2t = X2.reshape(batch, n, n).transpose(0, 2, 1).reshape(-1)
+        for ops in itertools.product("NT", repeat=2):
+            K = np.kron(opm(A, ops[0]), opm(B, ops[1]))
+            base = (X2t.reshape(batch, n * n) @ K.T).reshape(-1)
+            got = orc.kron2d_ex(n, ops[0], ops[1], 0.75, A, B, X2, -1.0, Y2, batch, opX="T")
+            assert rel(got, 0.75 * base - Y2) < 1e-13, ("2d opX", ops)
 
 
 ALL_PINS = [

@@ -58,6 +58,30 @@ def test_ex3d_matches_brute_force(n, ops):
         np.testing.assert_allclose(got, want, rtol=1e-13, atol=1e-13)
 
 
+@pytest.mark.parametrize("n", [1, 2, 4])
+@pytest.mark.parametrize("ops", list(itertools.product("NT", repeat=2)))
+def test_ex2d_op_x_matches_brute_force(n, ops):
+    """op(X_p) = X_p^T in 2-D (Section 2.2): brute force on explicitly
+    transposed operands; op(X) = N is the plain extended call."""
+    rng = np.random.default_rng(300 + n)
+    batch = 6
+    A, B = rng.uniform(-1, 1, n * n), rng.uniform(-1, 1, n * n)
+    X = rng.standard_normal(batch * n * n)
+    Y0 = rng.standard_normal(batch * n * n)
+    Xt = X.reshape(batch, n, n).transpose(0, 2, 1).reshape(-1)
+    for alpha, beta in ((1.0, 0.0), (-2.0, 0.5)):
+        got = oracle.kron2d_ex(n, ops[0], ops[1], alpha, A, B, X, beta, Y0, batch, opX="T")
+        want = alpha * _brute2d(n, ops[0], ops[1], A, B, Xt, batch) + beta * Y0
+        np.testing.assert_allclose(got, want, rtol=1e-13, atol=1e-13)
+        plain = oracle.kron2d_ex(n, ops[0], ops[1], alpha, A, B, X, beta, Y0, batch, opX="N")
+        np.testing.assert_allclose(plain, oracle.kron2d_ex(n, ops[0], ops[1], alpha, A, B, X, beta, Y0, batch),
+                                   rtol=0, atol=0)
+    if n > 1:
+        # the transposed operand differs from the plain one
+        assert not np.allclose(oracle.kron2d_ex(n, "N", "N", 1.0, A, B, X, 0.0, Y0, batch, opX="T"),
+                               oracle.kron2d_ex(n, "N", "N", 1.0, A, B, X, 0.0, Y0, batch))
+
+
 def test_ex_beta_zero_does_not_read_y():
     rng = np.random.default_rng(7)
     n, batch = 4, 3
