@@ -248,6 +248,38 @@ def measure_ex(torch, steps, warmup, beta=0.0):
             "sampled_rel_err": float(np.sqrt(num / den))}
 
 
+def measure_ex2d_transx(torch, steps, warmup):
+    """2-D n=16 FP32 with op(X_p) = X_p^T (Section 2.2's 2-D interface):
+    operands read transposed, beta = 0 (2 GiB of traffic)."""
+    import paper_1304_7054_amd as kron
+    import workloads
+    n, batch = 16, workloads.BATCH_2D[16]
+    mats, X, Y = make_inputs(torch, 2, n, batch, "f32", 6)
+    ws = torch.empty(kron.kron_ex_workspace_size(2, n, kron.MODE_F32), dtype=torch.uint8, device="cuda")
+    fn = lambda stream=None: kron.kron2d_batched_ex_f32(n, "N", "N", "T", 1.0, *mats, X, 0.0, Y, batch, ws, stream)
+    wall, kmean, kmin = time_launches(torch, fn, (), max(10, steps // 2), warmup)
+    torch.cuda.synchronize()
+    import oracle
+    rng = np.random.default_rng(6)
+    hm = [m.double().cpu().numpy() for m in mats]
+    e, num, den = n * n, 0.0, 0.0
+    for q in rng.integers(0, batch, 16):
+        x = X[q * e:(q + 1) * e].double().cpu().numpy()
+        want = oracle.kron2d_ex(n, "N", "N", 1.0, *hm, x, 0.0, np.zeros(e), 1, opX="T")
+        got = Y[q * e:(q + 1) * e].double().cpu().numpy()
+        num += float(np.sum((got - want) ** 2))
+        den += float(np.sum(want ** 2))
+    alg = 2 * X.numel() * 4
+    del mats, X, Y, ws
+    torch.cuda.empty_cache()
+    return {"mode": "f32 extended 2-D n=16 (op(X) = X^T, beta=0)", "batch": batch, "ms": round(kmean, 4),
+            "ms_min": round(kmin, 4), "wall_ms_per_step": round(wall, 4),
+            "gflops": round(batch * flops_per_op(2, n) / (kmean * 1e-3) / 1e9, 1),
+            "gbs": round(alg / (kmean * 1e-3) / 1e9, 1),
+            "hbm_frac": round(alg / (kmean * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "alg_bytes": alg,
+            "sampled_rel_err": float(np.sqrt(num / den))}
+
+
 def measure_backward(torch, steps, warmup):
     """dX + dA + dB + dC of the 3-D n=16 FP32 workload (reads X and dY,
     writes dX: three 1 GiB streams)."""
@@ -527,6 +559,9 @@ def main():
             others.append(measure_ex(torch, args.steps, args.warmup, beta))
             print(f"# measured extended interface, beta={beta}: {others[-1]['gflops']} GFLOP/s", file=sys.stderr,
                   flush=True)
+        others.append(measure_ex2d_transx(torch, args.steps, args.warmup))
+        print(f"# measured extended interface 2-D op(X)=T: {others[-1]['gflops']} GFLOP/s", file=sys.stderr,
+              flush=True)
         others.append(measure_backward(torch, args.steps, args.warmup))
         print(f"# measured backward: {others[-1]['ms']} ms", file=sys.stderr, flush=True)
 

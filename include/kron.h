@@ -164,8 +164,9 @@ int kron_graph_destroy(void* graph_exec);
 
 /* Y_p <- alpha * K(op(A), op(B)[, op(C)]) X_p + beta * Y_p (Section 2.2's
    batched update) with op(M) = M ('N' or 'n') or M^T ('T' or 't'), on the
-   same storage as the plain entry points (2-D: Y_p = alpha * op(B) X_p
-   op(A)^T + beta * Y_p; 3-D: vec(Y_p) = alpha * (op(A) (x) op(B) (x) op(C))
+   same storage as the plain entry points (2-D: Y_p = alpha * op(B) op(X_p)
+   op(A)^T + beta * Y_p, where opX may transpose each operand as the paper's
+   2-D interface allows; 3-D: vec(Y_p) = alpha * (op(A) (x) op(B) (x) op(C))
    vec(X_p) + beta * vec(Y_p)).  Following the paper's transpose-once remark
    (Section 2.2), op and alpha are applied once to the n x n factors, written
    to the caller's workspace `ws` (device memory aligned to the element size,
@@ -177,14 +178,16 @@ int kron_graph_destroy(void* graph_exec);
    beta != 0: every output element is read once and updated in place by the
    lane that computes it (one more pass over Y; NaN in Y propagates as in
    BLAS).
+   opX = 'T' (2-D): each X_p is read transposed by the computing lanes (no
+   copy of X is made).
    Returns 0 or -k (argument k invalid; a bad op character counts as
    invalid); batch == 0 is a no-op.  Asynchronous on `stream`; `ws` must stay
    valid until the call's kernels have run. */
 size_t kron_ex_workspace_size(int dim, int n, int mode);
-int kron2d_batched_ex_f32(int n, char opA, char opB, float alpha, const float* A, const float* B,
+int kron2d_batched_ex_f32(int n, char opA, char opB, char opX, float alpha, const float* A, const float* B,
                           const float* X, float beta, float* Y, int64_t batch, void* ws, size_t ws_bytes,
                           hipStream_t stream);
-int kron2d_batched_ex_f64(int n, char opA, char opB, double alpha, const double* A, const double* B,
+int kron2d_batched_ex_f64(int n, char opA, char opB, char opX, double alpha, const double* A, const double* B,
                           const double* X, double beta, double* Y, int64_t batch, void* ws, size_t ws_bytes,
                           hipStream_t stream);
 int kron3d_batched_ex_f32(int n, char opA, char opB, char opC, float alpha, const float* A, const float* B,

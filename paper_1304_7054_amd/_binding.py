@@ -55,8 +55,8 @@ SIGNATURES = {
     "kron3d_backward_f32": "ippppppppplpzS",
     "kron2d_backward_f64": "ippppppplpzS",
     "kron3d_backward_f64": "ippppppppplpzS",
-    "kron2d_batched_ex_f32": "iccfpppfplpzS",
-    "kron2d_batched_ex_f64": "iccdpppdplpzS",
+    "kron2d_batched_ex_f32": "icccfpppfplpzS",
+    "kron2d_batched_ex_f64": "icccdpppdplpzS",
     "kron3d_batched_ex_f32": "icccfppppfplpzS",
     "kron3d_batched_ex_f64": "icccdppppdplpzS",
 }
@@ -308,19 +308,19 @@ def _ex_call(name, dim, dtype, mode, n, ops, alpha, mats, X, beta, Y, batch, ws,
     return _call(name, n, *opc, alpha, *ptrs, px, beta, py, batch, pw, ws.numel(), _stream(stream))
 
 
-def kron2d_batched_ex_f32(n, opA, opB, alpha, A, B, X, beta, Y, batch, ws=None, stream=None):
-    """Y_p = alpha op(B) X_p op(A)^T, FP32 (beta must be 0; see include/kron.h)."""
-    return _ex_call("kron2d_batched_ex_f32", 2, torch.float32, MODE_F32, n, (opA, opB), float(alpha), (A, B), X,
-                    float(beta), Y, batch, ws, stream)
+def kron2d_batched_ex_f32(n, opA, opB, opX, alpha, A, B, X, beta, Y, batch, ws=None, stream=None):
+    """Y_p = alpha op(B) op(X_p) op(A)^T + beta Y_p, FP32 (see include/kron.h)."""
+    return _ex_call("kron2d_batched_ex_f32", 2, torch.float32, MODE_F32, n, (opA, opB, opX), float(alpha), (A, B),
+                    X, float(beta), Y, batch, ws, stream)
 
 
-def kron2d_batched_ex_f64(n, opA, opB, alpha, A, B, X, beta, Y, batch, ws=None, stream=None):
-    return _ex_call("kron2d_batched_ex_f64", 2, torch.float64, MODE_F64, n, (opA, opB), float(alpha), (A, B), X,
-                    float(beta), Y, batch, ws, stream)
+def kron2d_batched_ex_f64(n, opA, opB, opX, alpha, A, B, X, beta, Y, batch, ws=None, stream=None):
+    return _ex_call("kron2d_batched_ex_f64", 2, torch.float64, MODE_F64, n, (opA, opB, opX), float(alpha), (A, B),
+                    X, float(beta), Y, batch, ws, stream)
 
 
 def kron3d_batched_ex_f32(n, opA, opB, opC, alpha, A, B, C, X, beta, Y, batch, ws=None, stream=None):
-    """vec(Y_p) = alpha (op(A) kron op(B) kron op(C)) vec(X_p), FP32 (beta must be 0)."""
+    """vec(Y_p) = alpha (op(A) kron op(B) kron op(C)) vec(X_p) + beta vec(Y_p), FP32."""
     return _ex_call("kron3d_batched_ex_f32", 3, torch.float32, MODE_F32, n, (opA, opB, opC), float(alpha),
                     (A, B, C), X, float(beta), Y, batch, ws, stream)
 

@@ -150,22 +150,26 @@ __global__ __launch_bounds__(256) void kron_prepare_factors_kernel(int n, int nf
 // 0 for 'N'/'n', 1 for 'T'/'t', -1 otherwise
 int op_bit(char op) { return (op == 'N' || op == 'n') ? 0 : (op == 'T' || op == 't') ? 1 : -1; }
 
-// Checks and factor preparation shared by the extended entry points (positions
-// follow their C signatures: n, the ops, alpha, the factors, X, beta, Y,
-// batch, ws, ws_bytes).  Returns 0, with the prepared factors being written
-// to ws on `stream`, or -k.
+// Checks and factor preparation shared by the extended entry points.
+// Positions follow their C signatures: n, the ops (one per factor, then opX
+// in 2-D), alpha, the factors, X, beta, Y, batch, ws, ws_bytes.  Returns 0,
+// with the prepared factors being written to ws on `stream` and *transx set,
+// or -k.
 template <typename T>
-int prepare_ex(int dim, int n, const char* ops, T alpha, const T* const* mats, const T* X, T beta, const T* Y,
-               int64_t batch, void* ws, size_t ws_bytes, hipStream_t stream, bool* skip) {
+int prepare_ex(int dim, int n, const char* ops, T alpha, const T* const* mats, const T* X, const T* Y,
+               int64_t batch, void* ws, size_t ws_bytes, hipStream_t stream, bool* skip, bool* transx) {
   *skip = false;
+  *transx = false;
   if (n < 1 || n > KRON_MAX_N) return -1;
+  const int nops = 3;  // 2-D: opA, opB, opX; 3-D: opA, opB, opC
   unsigned tmask = 0;
-  for (int f = 0; f < dim; ++f) {
+  for (int f = 0; f < nops; ++f) {
     const int b = op_bit(ops[f]);
     if (b < 0) return -(2 + f);
-    tmask |= (unsigned)b << f;
+    if (f < dim) tmask |= (unsigned)b << f;
+    else *transx = b != 0;
   }
-  const int kA = 2 + dim + 1;  // position of A (after n, the ops and alpha)
+  const int kA = nops + 3;  // position of A (after n, the ops and alpha)
   for (int f = 0; f < dim; ++f)
     if (!mats[f]) return -(kA + f);
   const int kX = kA + dim;
@@ -418,29 +422,32 @@ size_t kron_ex_workspace_size(int dim, int n, int mode) {
   return (size_t)dim * n * n * (mode == KRON_MODE_F64 ? 8 : 4);
 }
 
-int kron2d_batched_ex_f32(int n, char opA, char opB, float alpha, const float* A, const float* B, const float* X,
-                          float beta, float* Y, int64_t batch, void* ws, size_t ws_bytes, hipStream_t stream) {
-  const char ops[2] = {opA, opB};
+int kron2d_batched_ex_f32(int n, char opA, char opB, char opX, float alpha, const float* A, const float* B,
+                          const float* X, float beta, float* Y, int64_t batch, void* ws, size_t ws_bytes,
+                          hipStream_t stream) {
+  const char ops[3] = {opA, opB, opX};
   const float* mats[2] = {A, B};
-  bool skip;
-  if (int rc = prepare_ex<float>(2, n, ops, alpha, mats, X, beta, Y, batch, ws, ws_bytes, stream, &skip)) return rc;
+  bool skip, transx;
+  if (int rc = prepare_ex<float>(2, n, ops, alpha, mats, X, Y, batch, ws, ws_bytes, stream, &skip, &transx))
+    return rc;
   if (skip) return 0;
   const float* P = static_cast<const float*>(ws);
-  return finish_launch(beta != 0.0f ? kron::beta2d_f32(n, P, P + n * n, X, Y, batch, beta, stream)
-                                     : kron::fwd2d_f32(n, P, P + n * n, X, Y, batch, stream, false));
+  return finish_launch(beta != 0.0f || transx ? kron::ex2d_f32(n, P, P + n * n, X, Y, batch, beta, transx, stream)
+                                              : kron::fwd2d_f32(n, P, P + n * n, X, Y, batch, stream, false));
 }
 
-int kron2d_batched_ex_f64(int n, char opA, char opB, double alpha, const double* A, const double* B,
+int kron2d_batched_ex_f64(int n, char opA, char opB, char opX, double alpha, const double* A, const double* B,
                           const double* X, double beta, double* Y, int64_t batch, void* ws, size_t ws_bytes,
                           hipStream_t stream) {
-  const char ops[2] = {opA, opB};
+  const char ops[3] = {opA, opB, opX};
   const double* mats[2] = {A, B};
-  bool skip;
-  if (int rc = prepare_ex<double>(2, n, ops, alpha, mats, X, beta, Y, batch, ws, ws_bytes, stream, &skip)) return rc;
+  bool skip, transx;
+  if (int rc = prepare_ex<double>(2, n, ops, alpha, mats, X, Y, batch, ws, ws_bytes, stream, &skip, &transx))
+    return rc;
   if (skip) return 0;
   const double* P = static_cast<const double*>(ws);
-  return finish_launch(beta != 0.0 ? kron::beta2d_f64(n, P, P + n * n, X, Y, batch, beta, stream)
-                                    : kron::fwd2d_f64(n, P, P + n * n, X, Y, batch, stream, false));
+  return finish_launch(beta != 0.0 || transx ? kron::ex2d_f64(n, P, P + n * n, X, Y, batch, beta, transx, stream)
+                                             : kron::fwd2d_f64(n, P, P + n * n, X, Y, batch, stream, false));
 }
 
 int kron3d_batched_ex_f32(int n, char opA, char opB, char opC, float alpha, const float* A, const float* B,
@@ -448,11 +455,12 @@ int kron3d_batched_ex_f32(int n, char opA, char opB, char opC, float alpha, cons
                           size_t ws_bytes, hipStream_t stream) {
   const char ops[3] = {opA, opB, opC};
   const float* mats[3] = {A, B, C};
-  bool skip;
-  if (int rc = prepare_ex<float>(3, n, ops, alpha, mats, X, beta, Y, batch, ws, ws_bytes, stream, &skip)) return rc;
+  bool skip, transx;
+  if (int rc = prepare_ex<float>(3, n, ops, alpha, mats, X, Y, batch, ws, ws_bytes, stream, &skip, &transx))
+    return rc;
   if (skip) return 0;
   const float* P = static_cast<const float*>(ws);
-  return finish_launch(beta != 0.0f ? kron::beta3d_f32(n, P, P + n * n, P + 2 * n * n, X, Y, batch, beta, stream)
+  return finish_launch(beta != 0.0f ? kron::ex3d_f32(n, P, P + n * n, P + 2 * n * n, X, Y, batch, beta, stream)
                                      : kron::fwd3d_f32(n, P, P + n * n, P + 2 * n * n, X, Y, batch, stream, false));
 }
 
@@ -461,11 +469,12 @@ int kron3d_batched_ex_f64(int n, char opA, char opB, char opC, double alpha, con
                           size_t ws_bytes, hipStream_t stream) {
   const char ops[3] = {opA, opB, opC};
   const double* mats[3] = {A, B, C};
-  bool skip;
-  if (int rc = prepare_ex<double>(3, n, ops, alpha, mats, X, beta, Y, batch, ws, ws_bytes, stream, &skip)) return rc;
+  bool skip, transx;
+  if (int rc = prepare_ex<double>(3, n, ops, alpha, mats, X, Y, batch, ws, ws_bytes, stream, &skip, &transx))
+    return rc;
   if (skip) return 0;
   const double* P = static_cast<const double*>(ws);
-  return finish_launch(beta != 0.0 ? kron::beta3d_f64(n, P, P + n * n, P + 2 * n * n, X, Y, batch, beta, stream)
+  return finish_launch(beta != 0.0 ? kron::ex3d_f64(n, P, P + n * n, P + 2 * n * n, X, Y, batch, beta, stream)
                                     : kron::fwd3d_f64(n, P, P + n * n, P + 2 * n * n, X, Y, batch, stream, false));
 }
 

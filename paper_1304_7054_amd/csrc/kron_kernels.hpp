@@ -119,7 +119,10 @@ struct AxisPart {
 
 // ---- 2-D tile ---------------------------------------------------------------------
 
-template <class M, int N, bool kVec, bool kTrans>
+// kTX: the operands are read transposed (op(X_p) = X_p^T of Section 2.2's
+// 2-D interface): the slow and fast element strides of the loads swap, the
+// packed-operand numbering does not, and the loads are scalar.
+template <class M, int N, bool kVec, bool kTrans, bool kTX = false>
 struct Tile2D {
   using io_t = typename M::io_t;
   using acc_t = typename M::acc_t;
@@ -133,19 +136,23 @@ struct Tile2D {
   static constexpr bool kRegroup = kVec && M::drow(0, 1) != 1;
   static constexpr bool kStoreVec = kVec;
 
+  static constexpr bool kLoadVec = kVec && !kTX;
+
   fac_t fB, fA;
-  AxisPart<N, E> pL;            // slot L on the slow axis (load and store)
+  AxisPart<N, E> pL;            // slot L on the slow axis (store)
+  AxisPart<N, E> pLi;           // slot L on the slow axis (load; stride 1 when kTX)
   int offI[4], opI[4];          // load: fast slots 4g + s
   bool vI[4];
   int offO[4], opO[4];          // store: fast slots drow(g, r)
   bool vO[4];
 
-  __device__ __forceinline__ Tile2D(const io_t* A, const io_t* B, int L, int g) : pL(L, N, Q) {
+  __device__ __forceinline__ Tile2D(const io_t* A, const io_t* B, int L, int g)
+      : pL(L, N, Q), pLi(L, kTX ? 1 : N, Q) {
     fB = M::template load_fac<N, kTrans>(B, L, g, 0);
     fA = M::template load_fac<N, kTrans>(A, L, g, 1);
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-      AxisPart<N, E> pi(4 * g + s, 1, 1), po(kRegroup ? 4 * g + s : M::drow(g, s), 1, 1);
+      AxisPart<N, E> pi(4 * g + s, kTX ? N : 1, 1), po(kRegroup ? 4 * g + s : M::drow(g, s), 1, 1);
       offI[s] = pi.off; opI[s] = pi.op; vI[s] = pi.valid;
       offO[s] = po.off; opO[s] = po.op; vO[s] = po.valid;
     }
@@ -159,17 +166,17 @@ struct Tile2D {
 
   __device__ __forceinline__ acc_t load(const io_t* Xt, int64_t rem, int only = -1) const {
     acc_t x;
-    if constexpr (N == 16 && kVec) {
-      x = Mem<io_t>::load4(Xt + pL.off + offI[0]);
-    } else if constexpr (kVec) {
-      bool ok = pL.valid && vI[0] && take(pL.op + opI[0], rem, only);
-      if (ok) x = Mem<io_t>::load4(Xt + pL.off + offI[0]);
+    if constexpr (N == 16 && kLoadVec) {
+      x = Mem<io_t>::load4(Xt + pLi.off + offI[0]);
+    } else if constexpr (kLoadVec) {
+      bool ok = pLi.valid && vI[0] && take(pLi.op + opI[0], rem, only);
+      if (ok) x = Mem<io_t>::load4(Xt + pLi.off + offI[0]);
       else x = acc_t{0, 0, 0, 0};
     } else {
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
-        bool ok = pL.valid && vI[s] && take(pL.op + opI[s], rem, only);
-        x[s] = ok ? Mem<io_t>::load1(Xt + pL.off + offI[s]) : 0;
+        bool ok = pLi.valid && vI[s] && take(pLi.op + opI[s], rem, only);
+        x[s] = ok ? Mem<io_t>::load1(Xt + pLi.off + offI[s]) : 0;
       }
     }
     return x;
@@ -516,24 +523,28 @@ __global__ __launch_bounds__(kBlock) void kron3d_kernel(const typename M::io_t* 
   }
 }
 
-// Y_p <- K X_p + beta Y_p for beta != 0 (Section 3's output update; alpha is
-// folded into the factors by the caller).  The tile loops of the plain
-// kernels (2-D: four tiles in flight per wavefront; 3-D: contiguous 1 KiB
-// rows), with every lane reading the old output where it stores.  FP32 and
-// FP64 storage only (io_t is the arithmetic type).
-template <class M, int N, bool kVec, int kDim>
-__global__ __launch_bounds__(kBlock) void kron_beta_kernel(const typename M::io_t* __restrict__ A,
-                                                           const typename M::io_t* __restrict__ B,
-                                                           const typename M::io_t* __restrict__ C,
-                                                           const typename M::io_t* __restrict__ X,
-                                                           typename M::io_t* __restrict__ Y, int64_t batch,
-                                                           int64_t ntiles, typename M::io_t beta) {
+// The extended interface's cases that the plain kernels do not cover
+// (Section 2.2's update Y_p <- K(op(X_p)) + beta Y_p; alpha and op on the
+// factors are folded into the factors by the caller):
+//   kBeta  beta != 0: every lane reads the old output where it stores;
+//   kTX    (2-D) the operands are read transposed.
+// The tile loops of the plain kernels: 2-D keeps four tiles in flight per
+// wavefront, 3-D walks contiguous 1 KiB rows.  FP32 and FP64 storage only
+// (io_t is the arithmetic type).
+template <class M, int N, bool kVec, int kDim, bool kBeta, bool kTX>
+__global__ __launch_bounds__(kBlock) void kron_ex_kernel(const typename M::io_t* __restrict__ A,
+                                                         const typename M::io_t* __restrict__ B,
+                                                         const typename M::io_t* __restrict__ C,
+                                                         const typename M::io_t* __restrict__ X,
+                                                         typename M::io_t* __restrict__ Y, int64_t batch,
+                                                         int64_t ntiles, typename M::io_t beta) {
+  static_assert(kDim == 2 || !kTX, "op on the operands exists in 2-D only");
   using acc_t = typename M::acc_t;
   const int l = threadIdx.x & 63, L = l & 15, g = l >> 4;
   const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * kBlock) >> 6;
   if constexpr (kDim == 2) {
-    using T = Tile2D<M, N, kVec, false>;
+    using T = Tile2D<M, N, kVec, false, kTX>;
     constexpr int kTiles = 4;
     const T tile(A, B, L, g);
     for (int64_t base = wave * kTiles; base < ntiles; base += nwaves * kTiles) {
@@ -550,7 +561,8 @@ __global__ __launch_bounds__(kBlock) void kron_beta_kernel(const typename M::io_
       for (int j = 0; j < kTiles; ++j) {
         const int64_t t = base + j;
         if (t < ntiles)
-          tile.template finish<true>(X + t * T::kOps * T::E, Y + t * T::kOps * T::E, batch - t * T::kOps, x[j], beta);
+          tile.template finish<kBeta>(X + t * T::kOps * T::E, Y + t * T::kOps * T::E, batch - t * T::kOps, x[j],
+                                      beta);
       }
     }
   } else {
@@ -561,7 +573,7 @@ __global__ __launch_bounds__(kBlock) void kron_beta_kernel(const typename M::io_
       acc_t v[16];
       tile.load(X + t * kStep, batch - t * T::kOps, v);
       tile.compute(v);
-      tile.template finish<true>(X + t * kStep, Y + t * kStep, batch - t * T::kOps, v, beta);
+      tile.template finish<kBeta>(X + t * kStep, Y + t * kStep, batch - t * T::kOps, v, beta);
     }
   }
 }

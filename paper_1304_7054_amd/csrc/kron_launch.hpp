@@ -187,12 +187,12 @@ int launch3d_n(const typename M::io_t* A, const typename M::io_t* B, const typen
   return 0;
 }
 
-// beta != 0 (kron_beta_kernel): the vector path when X and Y are aligned,
-// a persistent grid sized by occupancy.
-template <class M, int Dim, int N>
-int launch_beta_n(const typename M::io_t* A, const typename M::io_t* B, const typename M::io_t* C,
-                  const typename M::io_t* X, typename M::io_t* Y, int64_t batch, typename M::io_t beta,
-                  hipStream_t stream) {
+// kron_ex_kernel (beta != 0, or 2-D operands read transposed): the vector
+// path when X and Y are aligned, a persistent grid sized by occupancy.
+template <class M, int Dim, int N, bool kBeta, bool kTX>
+void launch_ex_k(const typename M::io_t* A, const typename M::io_t* B, const typename M::io_t* C,
+                 const typename M::io_t* X, typename M::io_t* Y, int64_t batch, typename M::io_t beta,
+                 hipStream_t stream) {
   using io_t = typename M::io_t;
   constexpr int64_t Q = Geo<N>::Q;
   constexpr int64_t ops = Dim == 2 ? Q * Q : Q * Q * Q;
@@ -204,11 +204,27 @@ int launch_beta_n(const typename M::io_t* A, const typename M::io_t* B, const ty
   };
   if constexpr (Geo<N>::kVec) {
     if (aligned_to(X, Mem<io_t>::kAlign) && aligned_to(Y, Mem<io_t>::kAlign)) {
-      run(kron_beta_kernel<M, N, true, Dim>);
+      run(kron_ex_kernel<M, N, true, Dim, kBeta, kTX>);
+      return;
+    }
+  }
+  run(kron_ex_kernel<M, N, false, Dim, kBeta, kTX>);
+}
+
+template <class M, int Dim, int N>
+int launch_ex_n(const typename M::io_t* A, const typename M::io_t* B, const typename M::io_t* C,
+                const typename M::io_t* X, typename M::io_t* Y, int64_t batch, typename M::io_t beta, bool transx,
+                hipStream_t stream) {
+  const bool has_beta = beta != typename M::io_t(0);
+  if constexpr (Dim == 2) {
+    if (transx) {
+      if (has_beta) launch_ex_k<M, 2, N, true, true>(A, B, C, X, Y, batch, beta, stream);
+      else launch_ex_k<M, 2, N, false, true>(A, B, C, X, Y, batch, beta, stream);
       return 0;
     }
   }
-  run(kron_beta_kernel<M, N, false, Dim>);
+  if (!has_beta || transx) return -2;  // nothing this kernel adds: the caller runs the plain kernels
+  launch_ex_k<M, Dim, N, true, false>(A, B, C, X, Y, batch, beta, stream);
   return 0;
 }
 
@@ -230,13 +246,13 @@ int launch2d(int n, const typename M::io_t* A, const typename M::io_t* B, const 
 }
 
 template <class M, int Dim>
-int launch_beta(int n, const typename M::io_t* A, const typename M::io_t* B, const typename M::io_t* C,
-                const typename M::io_t* X, typename M::io_t* Y, int64_t batch, typename M::io_t beta,
-                hipStream_t stream) {
+int launch_ex(int n, const typename M::io_t* A, const typename M::io_t* B, const typename M::io_t* C,
+              const typename M::io_t* X, typename M::io_t* Y, int64_t batch, typename M::io_t beta, bool transx,
+              hipStream_t stream) {
   switch (n) {
 #define KRON_CASE(NN) \
   case NN:            \
-    return launch_beta_n<M, Dim, NN>(A, B, C, X, Y, batch, beta, stream);
+    return launch_ex_n<M, Dim, NN>(A, B, C, X, Y, batch, beta, transx, stream);
     KRON_N_CASES(KRON_CASE)
 #undef KRON_CASE
     default:

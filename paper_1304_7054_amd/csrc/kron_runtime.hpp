@@ -59,16 +59,18 @@ int fwd3d_bf16_lo(int n, const uint16_t* A, const uint16_t* B, const uint16_t* C
 int fwd3d_bf16_hi(int n, const uint16_t* A, const uint16_t* B, const uint16_t* C, const uint16_t* X, uint16_t* Y, int64_t batch,
                 hipStream_t s);
 
-// Y <- K X + beta Y with beta != 0 (kron_beta_<mode>.hip), alpha already in
-// the factors.  Return 0, or -1 for an n outside 1..16.
-int beta2d_f32(int n, const float* A, const float* B, const float* X, float* Y, int64_t batch, float beta,
-               hipStream_t s);
-int beta3d_f32(int n, const float* A, const float* B, const float* C, const float* X, float* Y, int64_t batch,
-               float beta, hipStream_t s);
-int beta2d_f64(int n, const double* A, const double* B, const double* X, double* Y, int64_t batch, double beta,
-               hipStream_t s);
-int beta3d_f64(int n, const double* A, const double* B, const double* C, const double* X, double* Y,
-               int64_t batch, double beta, hipStream_t s);
+// Y <- K(op(X)) + beta Y (kron_ex_<mode>.hip) for beta != 0 or, in 2-D,
+// transposed operands (transx); alpha and op on the factors are already in
+// the factors.  Return 0, -1 for an n outside 1..16, or -2 when beta == 0
+// and !transx (the plain kernels cover that case).
+int ex2d_f32(int n, const float* A, const float* B, const float* X, float* Y, int64_t batch, float beta, bool transx,
+             hipStream_t s);
+int ex3d_f32(int n, const float* A, const float* B, const float* C, const float* X, float* Y, int64_t batch,
+             float beta, hipStream_t s);
+int ex2d_f64(int n, const double* A, const double* B, const double* X, double* Y, int64_t batch, double beta,
+             bool transx, hipStream_t s);
+int ex3d_f64(int n, const double* A, const double* B, const double* C, const double* X, double* Y, int64_t batch,
+             double beta, hipStream_t s);
 
 // Grouped launch (kron_grouped.hip).
 size_t grouped_workspace_bytes(const struct kron_group* g, int ngroups);

@@ -2,7 +2,8 @@
 + beta Y (Section 3's batched interface with op in {N, T}), against the
 FP64 oracle's extended interface: every op combination, several n (tiled and
 staged paths, ragged batches), alpha values including 0 and negative ones.
-With beta = 0, Y starts as NaN so that an unwritten or read output shows;
+In 2-D, op may also transpose the operands (opX).  With beta = 0, Y starts
+as NaN so that an unwritten or read output shows;
 with beta != 0, Y starts as seeded values that the update must read.  A bad
 op character and a short or missing workspace are rejected with their
 argument's position."""
@@ -25,7 +26,7 @@ def _need_gpu():
         pytest.skip("no GPU")
 
 
-def _run(mode, dim, n, ops, alpha, batch, seed, beta=0.0, offset=0):
+def _run(mode, dim, n, ops, alpha, batch, seed, beta=0.0, offset=0, opX="N"):
     rng = np.random.default_rng(seed)
     mats = [rng.uniform(-1, 1, n * n) for _ in range(dim)]
     X = rng.standard_normal(batch * n ** dim)
@@ -44,13 +45,14 @@ def _run(mode, dim, n, ops, alpha, batch, seed, beta=0.0, offset=0):
         ty.copy_(torch.tensor(Y0, dtype=dt))
     hy0 = ty.double().cpu().numpy()
     fn = getattr(kron, f"kron{dim}d_batched_ex_{mode}")
-    assert fn(n, *ops, alpha, *tm, tx, beta, ty, batch) == 0
+    cops = tuple(ops) + ((opX,) if dim == 2 else ())
+    assert fn(n, *cops, alpha, *tm, tx, beta, ty, batch) == 0
     torch.cuda.synchronize()
     got = ty.double().cpu().numpy()
     hm = [t.double().cpu().numpy() for t in tm]
     hx = tx.double().cpu().numpy()
     if dim == 2:
-        want = oracle.kron2d_ex(n, *ops, alpha, *hm, hx, beta, hy0, batch)
+        want = oracle.kron2d_ex(n, *ops, alpha, *hm, hx, beta, hy0, batch, opX=opX)
     else:
         want = oracle.kron3d_ex(n, *ops, alpha, *hm, hx, beta, hy0, batch)
     assert np.all(np.isfinite(got))
@@ -131,6 +133,48 @@ def test_ex_beta_isolates_nonfinite_operands():
     np.testing.assert_allclose(got[keep], want[keep], rtol=1e-12, atol=1e-12)
 
 
+@pytest.mark.parametrize("mode", ["f32", "f64"])
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 8, 9, 12, 16])
+@pytest.mark.parametrize("beta", [0.0, -0.5])
+def test_ex2d_op_x(mode, n, beta):
+    """op(X_p) = X_p^T in 2-D, with and without the beta update, packed and
+    ragged tiles."""
+    _need_gpu()
+    _run(mode, 2, n, ("T", "N"), 1.25, 203, 500 + n, beta=beta, opX="T")
+
+
+@pytest.mark.parametrize("ops", list(itertools.product("NT", repeat=2)))
+def test_ex2d_op_x_all_factor_ops(ops):
+    _need_gpu()
+    _run("f32", 2, 16, ops, -1.0, 64, 77, opX="t")
+    _run("f64", 2, 7, ops, 0.5, 50, 78, beta=2.0, opX="T")
+
+
+@pytest.mark.parametrize("mode", ["f32", "f64"])
+def test_ex2d_op_x_unaligned(mode):
+    _need_gpu()
+    _run(mode, 2, 16, ("N", "N"), 1.0, 17, 14, beta=0.25, offset=1, opX="T")
+    _run(mode, 2, 6, ("N", "T"), 1.0, 17, 15, offset=3, opX="T")
+
+
+def test_ex2d_op_x_equals_transposed_input():
+    """opX = T gives bitwise what the plain action gives on explicitly
+    transposed operands (the same products in the same order)."""
+    _need_gpu()
+    g = torch.Generator(device="cuda").manual_seed(4)
+    n, batch = 16, 4096
+    A, B = (torch.rand(n * n, generator=g, device="cuda") - 0.5 for _ in range(2))
+    X = torch.randn(batch * n * n, generator=g, device="cuda")
+    Xt = X.view(batch, n, n).transpose(1, 2).contiguous().view(-1)
+    Y1, Y2 = torch.empty_like(X), torch.empty_like(X)
+    kron.kron2d_batched_ex_f32(n, "N", "N", "T", 1.0, A, B, X, 0.0, Y1, batch)
+    kron.kron2d_batched_ex_f32(n, "N", "N", "N", 1.0, A, B, Xt, 0.0, Y2, batch)
+    torch.cuda.synchronize()
+    # the two calls run different kernels (tile loop vs tuned kernel): same
+    # MFMA sequence per tile, so equal to rounding of the same sums
+    torch.testing.assert_close(Y1, Y2, rtol=0, atol=0)
+
+
 def test_ex_identity_ops_equal_plain_call():
     """op = N, alpha = 1 gives bitwise the plain entry point's result (the
     prepared factors are copies of the inputs and the same kernels run)."""
@@ -171,4 +215,10 @@ def test_ex_rejections():
     with pytest.raises(ValueError):       # short workspace, caught by the binding
         kron.kron3d_batched_ex_f32(n, "N", "N", "N", 1.0, *mats, X, 0.5, Y, batch, ws=ws[:8])
     with pytest.raises(ValueError):
-        kron.kron2d_batched_ex_f32(n, "X", "N", 1.0, mats[0], mats[1], X, 0.0, Y, batch)
+        kron.kron2d_batched_ex_f32(n, "X", "N", "N", 1.0, mats[0], mats[1], X, 0.0, Y, batch)
+    with pytest.raises(ValueError):
+        kron.kron2d_batched_ex_f32(n, "N", "N", "C", 1.0, mats[0], mats[1], X, 0.0, Y, batch)
+    # opX is argument 4 of the 2-D entry points
+    X2, Y2 = X[: batch * n * n], Y[: batch * n * n]
+    assert L.kron2d_batched_ex_f32(n, b"N", b"N", b"Q", 1.0, p[0], p[1], X2.data_ptr(), 0.0, Y2.data_ptr(), batch,
+                                   ws.data_ptr(), ws.numel(), s) == -4
