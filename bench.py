@@ -280,6 +280,48 @@ def measure_ex2d_transx(torch, steps, warmup):
             "sampled_rel_err": float(np.sqrt(num / den))}
 
 
+def measure_strided(torch, steps, warmup):
+    """3-D n=16 FP32 through the strided entry point on padded storage:
+    columns of 17 elements (ldx = ldy = 17, ldx2 = 17*16, ldxp = 17*256),
+    beta = 0.  Algorithmic bytes count the elements addressed (2 GiB)."""
+    import paper_1304_7054_amd as kron
+    import workloads
+    n, batch = 16, workloads.BATCH_3D[16]
+    ld = 17
+    ld2, ldp = ld * n, ld * n * n
+    g = torch.Generator(device="cuda").manual_seed(workloads.SEED_BASE + 7)
+    mats = [torch.rand(n * n, generator=g, device="cuda") * 2 - 1 for _ in range(3)]
+    X = torch.randn(ldp * batch, generator=g, device="cuda")
+    Y = torch.empty_like(X)
+    ws = torch.empty(kron.kron_ex_workspace_size(3, n, kron.MODE_F32), dtype=torch.uint8, device="cuda")
+    fn = lambda stream=None: kron.kron3d_batched_strided_f32(n, "N", "N", "N", 1.0, mats[0], n, mats[1], n, mats[2],
+                                                             n, X, ld, ld2, ldp, 0.0, Y, ld, ld2, ldp, batch, ws,
+                                                             stream)
+    wall, kmean, kmin = time_launches(torch, fn, (), max(10, steps // 2), warmup)
+    torch.cuda.synchronize()
+    import oracle
+    rng = np.random.default_rng(7)
+    hm = [m.double().cpu().numpy() for m in mats]
+    r = np.arange(n)
+    sub = (r[None, None, :] + ld * r[None, :, None] + ld2 * r[:, None, None]).reshape(-1)
+    num = den = 0.0
+    for q in rng.integers(0, batch, 16):
+        x = X[q * ldp:(q + 1) * ldp].double().cpu().numpy()[sub]
+        want = oracle.kron3d(n, *hm, x, 1)
+        got = Y[q * ldp:(q + 1) * ldp].double().cpu().numpy()[sub]
+        num += float(np.sum((got - want) ** 2))
+        den += float(np.sum(want ** 2))
+    alg = 2 * batch * n ** 3 * 4
+    del mats, X, Y, ws
+    torch.cuda.empty_cache()
+    return {"mode": "f32 strided 3-D n=16 (ld 17, padded columns, beta=0)", "batch": batch, "ms": round(kmean, 4),
+            "ms_min": round(kmin, 4), "wall_ms_per_step": round(wall, 4),
+            "gflops": round(batch * flops_per_op(3, n) / (kmean * 1e-3) / 1e9, 1),
+            "gbs": round(alg / (kmean * 1e-3) / 1e9, 1),
+            "hbm_frac": round(alg / (kmean * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "alg_bytes": alg,
+            "sampled_rel_err": float(np.sqrt(num / den))}
+
+
 def measure_backward(torch, steps, warmup):
     """dX + dA + dB + dC of the 3-D n=16 FP32 workload (reads X and dY,
     writes dX: three 1 GiB streams)."""
@@ -562,6 +604,8 @@ def main():
         others.append(measure_ex2d_transx(torch, args.steps, args.warmup))
         print(f"# measured extended interface 2-D op(X)=T: {others[-1]['gflops']} GFLOP/s", file=sys.stderr,
               flush=True)
+        others.append(measure_strided(torch, args.steps, args.warmup))
+        print(f"# measured strided 3-D: {others[-1]['gflops']} GFLOP/s", file=sys.stderr, flush=True)
         others.append(measure_backward(torch, args.steps, args.warmup))
         print(f"# measured backward: {others[-1]['ms']} ms", file=sys.stderr, flush=True)
 

@@ -197,6 +197,45 @@ int kron3d_batched_ex_f64(int n, char opA, char opB, char opC, double alpha, con
                           const double* C, const double* X, double beta, double* Y, int64_t batch, void* ws,
                           size_t ws_bytes, hipStream_t stream);
 
+/* ---- Section 3's interface with leading dimensions ------------------------------ */
+
+/* The extended update above on strided storage, with the argument layout of
+   the paper's TKRON2 / TKRON3 (Section 3) restricted to square n x n factors:
+     factor M (A, B, C): column-major with leading dimension ld >= n;
+     2-D operand p: X_p(l, m) at X[l + ldx*m + ldxp*p], result likewise in Y
+       with ldy, ldyp;
+     3-D operand p: X_p(l, m, k) at X[l + ldx*m + ldx2*k + ldxp*p] (l is the
+       fastest index, the one C contracts; ldx2 is the paper's distance
+       between adjacent planes), result likewise with ldy, ldy2, ldyp.
+   X is only read: its strides may be any values >= 0 (an operand stride of
+   0 applies the action to one array `batch` times).  Y's strides must give
+   every output element its own address: ldy >= n, ldy2 >= n*ldy (3-D), and
+   ldyp >= n*ldy (2-D) or n*ldy2 (3-D).  X and Y must not overlap.  The
+   library cannot see buffer sizes: the caller guarantees that every address
+   the strides reach lies inside its arrays.
+   ops, alpha, beta, ws (kron_ex_workspace_size bytes) and stream as for the
+   _ex entry points; opX (2-D) transposes each operand.  Every element is
+   read and written individually, so any stride and any element-aligned
+   address is accepted; contiguous arrays run faster through the _ex entry
+   points.  Returns 0 or -k (argument k invalid; positions beyond 15 are
+   reported by kron_status_string as "invalid argument"). */
+int kron2d_batched_strided_f32(int n, char opA, char opB, char opX, float alpha, const float* A, int lda,
+                               const float* B, int ldb, const float* X, int64_t ldx, int64_t ldxp, float beta,
+                               float* Y, int64_t ldy, int64_t ldyp, int64_t batch, void* ws, size_t ws_bytes,
+                               hipStream_t stream);
+int kron2d_batched_strided_f64(int n, char opA, char opB, char opX, double alpha, const double* A, int lda,
+                               const double* B, int ldb, const double* X, int64_t ldx, int64_t ldxp, double beta,
+                               double* Y, int64_t ldy, int64_t ldyp, int64_t batch, void* ws, size_t ws_bytes,
+                               hipStream_t stream);
+int kron3d_batched_strided_f32(int n, char opA, char opB, char opC, float alpha, const float* A, int lda,
+                               const float* B, int ldb, const float* C, int ldc, const float* X, int64_t ldx,
+                               int64_t ldx2, int64_t ldxp, float beta, float* Y, int64_t ldy, int64_t ldy2,
+                               int64_t ldyp, int64_t batch, void* ws, size_t ws_bytes, hipStream_t stream);
+int kron3d_batched_strided_f64(int n, char opA, char opB, char opC, double alpha, const double* A, int lda,
+                               const double* B, int ldb, const double* C, int ldc, const double* X, int64_t ldx,
+                               int64_t ldx2, int64_t ldxp, double beta, double* Y, int64_t ldy, int64_t ldy2,
+                               int64_t ldyp, int64_t batch, void* ws, size_t ws_bytes, hipStream_t stream);
+
 /* ---- backward ---------------------------------------------------------------- */
 
 /* Gradients of L = sum_p <dY_p, Y_p> for the forward actions above (the

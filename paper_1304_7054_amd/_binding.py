@@ -59,6 +59,10 @@ SIGNATURES = {
     "kron2d_batched_ex_f64": "icccdpppdplpzS",
     "kron3d_batched_ex_f32": "icccfppppfplpzS",
     "kron3d_batched_ex_f64": "icccdppppdplpzS",
+    "kron2d_batched_strided_f32": "icccfpipipllfplllpzS",
+    "kron2d_batched_strided_f64": "icccdpipiplldplllpzS",
+    "kron3d_batched_strided_f32": "icccfpipipiplllfpllllpzS",
+    "kron3d_batched_strided_f64": "icccdpipipipllldpllllpzS",
 }
 
 _CT = {"i": ctypes.c_int, "l": ctypes.c_int64, "p": ctypes.c_void_p, "S": ctypes.c_void_p,
@@ -328,6 +332,80 @@ def kron3d_batched_ex_f32(n, opA, opB, opC, alpha, A, B, C, X, beta, Y, batch, w
 def kron3d_batched_ex_f64(n, opA, opB, opC, alpha, A, B, C, X, beta, Y, batch, ws=None, stream=None):
     return _ex_call("kron3d_batched_ex_f64", 3, torch.float64, MODE_F64, n, (opA, opB, opC), float(alpha),
                     (A, B, C), X, float(beta), Y, batch, ws, stream)
+
+
+def _extent(n, strides):
+    """Elements spanned by one array with the given strides (fast stride 1),
+    from its first element to one past its last."""
+    return (n - 1) * (1 + sum(strides)) + 1
+
+
+def _strided_call(name, dim, dtype, mode, n, ops, alpha, mats, lds, X, ldx, beta, Y, ldy, batch, ws, stream):
+    n, batch = int(n), int(batch)
+    if not 1 <= n <= 16:
+        raise ValueError(f"n must be in 1..16, got {n}")
+    if batch < 0:
+        raise ValueError("batch must be >= 0")
+    opc = [_op_char(op, f"op{i}") for i, op in enumerate(ops)]
+    lds = [int(v) for v in lds]
+    ldx, ldy = [int(v) for v in ldx], [int(v) for v in ldy]
+    for i, ld in enumerate(lds):
+        if ld < n:
+            raise ValueError(f"leading dimension of factor {i} must be >= n")
+    if min(ldx) < 0:
+        raise ValueError("X strides must be >= 0")
+    if ldy[0] < n or any(ldy[j] < ldy[j - 1] * n for j in range(1, dim)):
+        raise ValueError("Y strides must give every output element its own address "
+                         "(ldy >= n, each further stride >= n times the previous)")
+    ptrs = []
+    for i, (M, ld) in enumerate(zip(mats, lds)):
+        ptrs += [_arr(M, dtype, (n - 1) * ld + n, f"factor {i}"), ld]
+    # one array spans its in-array strides; the batch adds (batch - 1) operand strides
+    ex = _extent(n, ldx[:-1]) + (batch - 1) * ldx[-1] if batch > 0 else 0
+    ey = _extent(n, ldy[:-1]) + (batch - 1) * ldy[-1] if batch > 0 else 0
+    px = _arr(X, dtype, ex, "X")
+    py = _arr(Y, dtype, ey, "Y")
+    if batch > 0:
+        esz = X.element_size()
+        x0, y0 = X.data_ptr(), Y.data_ptr()
+        if x0 < y0 + ey * esz and y0 < x0 + ex * esz:
+            raise ValueError("X and Y must not overlap")
+    need = kron_ex_workspace_size(dim, n, mode)
+    if ws is None:
+        ws = torch.empty(need, dtype=torch.uint8, device=Y.device)
+    pw = _arr(ws, torch.uint8, need, "workspace")
+    return _call(name, n, *opc, alpha, *ptrs, px, *ldx, beta, py, *ldy, batch, pw, ws.numel(), _stream(stream))
+
+
+def kron2d_batched_strided_f32(n, opA, opB, opX, alpha, A, lda, B, ldb, X, ldx, ldxp, beta, Y, ldy, ldyp, batch,
+                               ws=None, stream=None):
+    """Y_p = alpha op(B) op(X_p) op(A)^T + beta Y_p with leading dimensions
+    (X_p(l, m) at X[l + ldx*m + ldxp*p]), FP32 (see include/kron.h)."""
+    return _strided_call("kron2d_batched_strided_f32", 2, torch.float32, MODE_F32, n, (opA, opB, opX),
+                         float(alpha), (A, B), (lda, ldb), X, (ldx, ldxp), float(beta), Y, (ldy, ldyp), batch, ws,
+                         stream)
+
+
+def kron2d_batched_strided_f64(n, opA, opB, opX, alpha, A, lda, B, ldb, X, ldx, ldxp, beta, Y, ldy, ldyp, batch,
+                               ws=None, stream=None):
+    return _strided_call("kron2d_batched_strided_f64", 2, torch.float64, MODE_F64, n, (opA, opB, opX),
+                         float(alpha), (A, B), (lda, ldb), X, (ldx, ldxp), float(beta), Y, (ldy, ldyp), batch, ws,
+                         stream)
+
+
+def kron3d_batched_strided_f32(n, opA, opB, opC, alpha, A, lda, B, ldb, C, ldc, X, ldx, ldx2, ldxp, beta, Y, ldy,
+                               ldy2, ldyp, batch, ws=None, stream=None):
+    """3-D with leading dimensions: X_p(l, m, k) at X[l + ldx*m + ldx2*k + ldxp*p], FP32."""
+    return _strided_call("kron3d_batched_strided_f32", 3, torch.float32, MODE_F32, n, (opA, opB, opC),
+                         float(alpha), (A, B, C), (lda, ldb, ldc), X, (ldx, ldx2, ldxp), float(beta), Y,
+                         (ldy, ldy2, ldyp), batch, ws, stream)
+
+
+def kron3d_batched_strided_f64(n, opA, opB, opC, alpha, A, lda, B, ldb, C, ldc, X, ldx, ldx2, ldxp, beta, Y, ldy,
+                               ldy2, ldyp, batch, ws=None, stream=None):
+    return _strided_call("kron3d_batched_strided_f64", 3, torch.float64, MODE_F64, n, (opA, opB, opC),
+                         float(alpha), (A, B, C), (lda, ldb, ldc), X, (ldx, ldx2, ldxp), float(beta), Y,
+                         (ldy, ldy2, ldyp), batch, ws, stream)
 
 
 def _groups_array(groups):

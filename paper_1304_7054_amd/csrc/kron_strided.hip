@@ -1,0 +1,337 @@
+// Section 3's interface with leading dimensions: factors with lda/ldb/ldc,
+// operands and results at arbitrary element strides (ldx, ldx2, ldxp and
+// ldy, ldy2, ldyp), op on every factor, op on the operands in 2-D, alpha and
+// beta.  FP32 and FP64.
+//
+// The MFMA contractions are those of the dense tiles (Tile2D / Tile3D
+// compute); only the addressing differs.  Every lane computes the element
+// offsets of its slots from the strides at run time (64-bit), reads and
+// writes one element at a time, and keeps the dense kernels' rules: packed
+// tiles for n < 16, dead slots skipped, a tile with a non-finite result redone
+// one operand at a time.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kron.h"
+#include "kron_kernels.hpp"
+#include "kron_launch.hpp"
+
+namespace kron {
+namespace {
+
+// Element strides of one array: s1 between columns (2-D) or along the middle
+// index (3-D), s2 along the slowest index (3-D), sp between operands.
+struct Strides {
+  int64_t s1, s2, sp;
+};
+
+// op(M) with leading dimension ld, alpha on the first factor, written dense
+// (factor f at out + f * n^2, column-major).
+template <typename T>
+__global__ __launch_bounds__(256) void prepare_strided_factors_kernel(int n, int nf, const T* __restrict__ A, int lda,
+                                                                      const T* __restrict__ B, int ldb,
+                                                                      const T* __restrict__ C, int ldc, unsigned tmask,
+                                                                      T alpha, T* __restrict__ out) {
+  const int nn = n * n;
+  for (int e = threadIdx.x; e < nf * nn; e += blockDim.x) {
+    const int f = e / nn, idx = e % nn, i = idx % n, j = idx / n;
+    const T* M = f == 0 ? A : f == 1 ? B : C;
+    const int ld = f == 0 ? lda : f == 1 ? ldb : ldc;
+    const T v = ((tmask >> f) & 1u) ? M[j + (int64_t)ld * i] : M[i + (int64_t)ld * j];
+    out[e] = f == 0 ? alpha * v : v;
+  }
+}
+
+// One element access of a lane: its offset inside the tile's first operand
+// block and the packed operand it belongs to.
+struct Site {
+  int64_t off;
+  int op;
+  bool valid;
+};
+
+template <bool kBeta, typename T>
+__device__ __forceinline__ void put(T* p, T v, T beta) {
+  if constexpr (kBeta) v = v + beta * Mem<T>::load1(p);
+  Mem<T>::store1(p, v);
+}
+
+template <class M, int N, int kDim, bool kBeta, bool kTX>
+__global__ __launch_bounds__(kBlock) void kron_strided_kernel(const typename M::io_t* __restrict__ A,
+                                                              const typename M::io_t* __restrict__ B,
+                                                              const typename M::io_t* __restrict__ C,
+                                                              const typename M::io_t* __restrict__ X, Strides xs,
+                                                              typename M::io_t* __restrict__ Y, Strides ys,
+                                                              int64_t batch, int64_t ntiles, typename M::io_t beta) {
+  using io_t = typename M::io_t;
+  using acc_t = typename M::acc_t;
+  constexpr int Q = Geo<N>::Q;
+  const int l = threadIdx.x & 63, L = l & 15, g = l >> 4;
+  const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * kBlock) >> 6;
+  const Slot<N> sL(L);
+  if constexpr (kDim == 2) {
+    // lane (L, g) holds element (row = slot 4g + s, column = slot L) of op(X_p)
+    // and stores Y(row = slot drow(g, r), column = slot L)
+    using Tl = Tile2D<M, N, false, false>;
+    constexpr int kOps = Tl::kOps;
+    const Tl tile(A, B, L, g);
+    Site in[4], out[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const Slot<N> sf(4 * g + s), so(M::drow(g, s));
+      in[s].op = sL.sub * Q + sf.sub;
+      in[s].off = in[s].op * xs.sp + (kTX ? sL.idx + xs.s1 * sf.idx : sf.idx + xs.s1 * sL.idx);
+      in[s].valid = sL.valid && sf.valid;
+      out[s].op = sL.sub * Q + so.sub;
+      out[s].off = out[s].op * ys.sp + so.idx + ys.s1 * sL.idx;
+      out[s].valid = sL.valid && so.valid;
+    }
+    auto load = [&](const io_t* Xt, int64_t rem, int only) {
+      acc_t x;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const bool ok = in[s].valid && in[s].op < rem && (only < 0 || in[s].op == only);
+        x[s] = ok ? Mem<io_t>::load1(Xt + in[s].off) : io_t(0);
+      }
+      return x;
+    };
+    auto store = [&](io_t* Yt, int64_t rem, int only, const acc_t& y) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (out[r].valid && out[r].op < rem && (only < 0 || out[r].op == only)) put<kBeta>(Yt + out[r].off, y[r], beta);
+    };
+    for (int64_t t = wave; t < ntiles; t += nwaves) {
+      const io_t* Xt = X + t * kOps * xs.sp;
+      io_t* Yt = Y + t * kOps * ys.sp;
+      const int64_t rem = batch - t * kOps;
+      acc_t y = tile.compute(load(Xt, rem, -1));
+      if (kOps > 1 && __any(!all_finite(y))) {
+        const int last = rem < kOps ? (int)rem : kOps;
+        for (int o = 0; o < last; ++o) store(Yt, rem, o, tile.compute(load(Xt, rem, o)));
+      } else {
+        store(Yt, rem, -1, y);
+      }
+    }
+  } else {
+    // contiguous-row stage order of Tile3D: lane (L, g), slab b holds
+    // X(fast = slot 4g + s, middle = slot L, slow = slot b); results come back
+    // in the same arrangement
+    using Tl = Tile3D<M, N, false, false, true>;
+    constexpr int kOps = Tl::kOps;
+    const Tl tile(A, B, C, L, g);
+    Site fx[4], fy[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const Slot<N> sf(4 * g + s);
+      const int op = sL.sub * Q + sf.sub;
+      fx[s] = Site{op * xs.sp + sf.idx + xs.s1 * sL.idx, op, sL.valid && sf.valid};
+      fy[s] = Site{op * ys.sp + sf.idx + ys.s1 * sL.idx, op, sL.valid && sf.valid};
+    }
+    auto load = [&](const io_t* Xt, int64_t rem, int only, acc_t (&v)[16]) {
+#pragma unroll
+      for (int b = 0; b < 16; ++b) {
+        const Slot<N> sb(b);
+        const int opb = sb.sub * Q * Q;
+        const int64_t offb = opb * xs.sp + sb.idx * xs.s2;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const int op = opb + fx[s].op;
+          const bool ok = sb.valid && fx[s].valid && op < rem && (only < 0 || op == only);
+          v[b][s] = ok ? Mem<io_t>::load1(Xt + offb + fx[s].off) : io_t(0);
+        }
+      }
+    };
+    auto store = [&](io_t* Yt, int64_t rem, int only, const acc_t (&v)[16]) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const Slot<N> si(i);
+        const int opi = si.sub * Q * Q;
+        const int64_t offi = opi * ys.sp + si.idx * ys.s2;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const int op = opi + fy[s].op;
+          if (si.valid && fy[s].valid && op < rem && (only < 0 || op == only))
+            put<kBeta>(Yt + offi + fy[s].off, v[i][s], beta);
+        }
+      }
+    };
+    for (int64_t t = wave; t < ntiles; t += nwaves) {
+      const io_t* Xt = X + t * kOps * xs.sp;
+      io_t* Yt = Y + t * kOps * ys.sp;
+      const int64_t rem = batch - t * kOps;
+      acc_t v[16];
+      load(Xt, rem, -1, v);
+      tile.compute(v);
+      bool fin = true;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) fin = fin && all_finite(v[i]);
+      if (kOps > 1 && __any(!fin)) {
+        const int last = rem < kOps ? (int)rem : kOps;
+        for (int o = 0; o < last; ++o) {
+          load(Xt, rem, o, v);
+          tile.compute(v);
+          store(Yt, rem, o, v);
+        }
+      } else {
+        store(Yt, rem, -1, v);
+      }
+    }
+  }
+}
+
+template <class M, int Dim, int N, bool kBeta, bool kTX>
+void launch_strided_k(const typename M::io_t* A, const typename M::io_t* B, const typename M::io_t* C,
+                      const typename M::io_t* X, Strides xs, typename M::io_t* Y, Strides ys, int64_t batch,
+                      typename M::io_t beta, hipStream_t stream) {
+  constexpr int64_t Q = Geo<N>::Q;
+  constexpr int64_t ops = Dim == 2 ? Q * Q : Q * Q * Q;
+  const int64_t ntiles = (batch + ops - 1) / ops;
+  auto k = kron_strided_kernel<M, N, Dim, kBeta, kTX>;
+  hipLaunchKernelGGL(k, dim3(grid_blocks(ntiles, occupancy_blocks(k), 0)), dim3(kBlock), 0, stream, A, B, C, X, xs,
+                     Y, ys, batch, ntiles, beta);
+}
+
+template <class M, int Dim, int N>
+void launch_strided_n(const typename M::io_t* A, const typename M::io_t* B, const typename M::io_t* C,
+                      const typename M::io_t* X, Strides xs, typename M::io_t* Y, Strides ys, int64_t batch,
+                      typename M::io_t beta, bool transx, hipStream_t stream) {
+  const bool has_beta = beta != typename M::io_t(0);
+  if constexpr (Dim == 2) {
+    if (transx) {
+      if (has_beta) launch_strided_k<M, 2, N, true, true>(A, B, C, X, xs, Y, ys, batch, beta, stream);
+      else launch_strided_k<M, 2, N, false, true>(A, B, C, X, xs, Y, ys, batch, beta, stream);
+      return;
+    }
+  }
+  if (has_beta) launch_strided_k<M, Dim, N, true, false>(A, B, C, X, xs, Y, ys, batch, beta, stream);
+  else launch_strided_k<M, Dim, N, false, false>(A, B, C, X, xs, Y, ys, batch, beta, stream);
+}
+
+template <class M, int Dim>
+int launch_strided(int n, const typename M::io_t* A, const typename M::io_t* B, const typename M::io_t* C,
+                   const typename M::io_t* X, Strides xs, typename M::io_t* Y, Strides ys, int64_t batch,
+                   typename M::io_t beta, bool transx, hipStream_t stream) {
+  switch (n) {
+#define KRON_CASE(NN)                                                                           \
+  case NN:                                                                                      \
+    launch_strided_n<M, Dim, NN>(A, B, C, X, xs, Y, ys, batch, beta, transx, stream);           \
+    return 0;
+    KRON_N_CASES(KRON_CASE)
+#undef KRON_CASE
+    default:
+      return -1;
+  }
+}
+
+int op_code(char op) { return (op == 'N' || op == 'n') ? 0 : (op == 'T' || op == 't') ? 1 : -1; }
+
+// Argument checks and launches shared by the four entry points.  The
+// argument positions of the C signatures: n 1, the ops 2-4, alpha 5, then
+// (factor, ld) pairs from 6, then X and its strides, beta, Y and its
+// strides, batch, ws, ws_bytes.
+template <class M>
+int strided_call(int dim, int n, const char* ops, typename M::io_t alpha, const typename M::io_t* const* mats,
+                 const int* lds, const typename M::io_t* X, const int64_t* ldx, typename M::io_t beta,
+                 typename M::io_t* Y, const int64_t* ldy, int64_t batch, void* ws, size_t ws_bytes,
+                 hipStream_t stream) {
+  using T = typename M::io_t;
+  if (n < 1 || n > KRON_MAX_N) return -1;
+  unsigned tmask = 0;
+  bool transx = false;
+  for (int f = 0; f < 3; ++f) {
+    const int b = op_code(ops[f]);
+    if (b < 0) return -(2 + f);
+    if (f < dim) tmask |= (unsigned)b << f;
+    else transx = b != 0;
+  }
+  int k = 6;  // position of A
+  for (int f = 0; f < dim; ++f, k += 2) {
+    if (!mats[f]) return -k;
+    if (lds[f] < n) return -(k + 1);
+  }
+  // X: pointer at k, then its dim strides (ldx, [ldx2,] ldxp)
+  const int kX = k, kBeta = kX + dim + 1, kY = kBeta + 1, kBatch = kY + dim + 1;
+  if (!X || reinterpret_cast<uintptr_t>(X) % sizeof(T) != 0) return -kX;
+  if (!Y || reinterpret_cast<uintptr_t>(Y) % sizeof(T) != 0 || (const void*)Y == (const void*)X) return -kY;
+  // X is only read, so its strides may be any non-negative values (an
+  // operand stride of 0 applies the action to one array batch times).  Y's
+  // must give every output element its own address: ldy >= n, and each
+  // further stride at least n times the previous one.
+  for (int j = 0; j < dim; ++j)
+    if (ldx[j] < 0) return -(kX + 1 + j);
+  if (ldy[0] < n) return -(kY + 1);
+  for (int j = 1; j < dim; ++j)
+    if (ldy[j] < ldy[j - 1] * n) return -(kY + 1 + j);
+  if (batch < 0) return -kBatch;
+  if (batch == 0) return 0;
+  if (!ws || reinterpret_cast<uintptr_t>(ws) % sizeof(T) != 0) return -(kBatch + 1);
+  if (ws_bytes < (size_t)dim * n * n * sizeof(T)) return -(kBatch + 2);
+  T* P = static_cast<T*>(ws);
+  hipLaunchKernelGGL(prepare_strided_factors_kernel<T>, dim3(1), dim3(256), 0, stream, n, dim, mats[0], lds[0],
+                     mats[1], lds[1], dim == 3 ? mats[2] : mats[1], dim == 3 ? lds[2] : lds[1], tmask, alpha, P);
+  const Strides xs{ldx[0], dim == 3 ? ldx[1] : 0, ldx[dim - 1]};
+  const Strides ys{ldy[0], dim == 3 ? ldy[1] : 0, ldy[dim - 1]};
+  const int rc = dim == 2 ? launch_strided<M, 2>(n, P, P + n * n, P + n * n, X, xs, Y, ys, batch, beta, transx, stream)
+                          : launch_strided<M, 3>(n, P, P + n * n, P + 2 * n * n, X, xs, Y, ys, batch, beta, false,
+                                                 stream);
+  if (rc != 0) return rc;
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? 0 : (int)e;
+}
+
+}  // namespace
+}  // namespace kron
+
+extern "C" {
+
+int kron2d_batched_strided_f32(int n, char opA, char opB, char opX, float alpha, const float* A, int lda,
+                               const float* B, int ldb, const float* X, int64_t ldx, int64_t ldxp, float beta,
+                               float* Y, int64_t ldy, int64_t ldyp, int64_t batch, void* ws, size_t ws_bytes,
+                               hipStream_t stream) {
+  const char ops[3] = {opA, opB, opX};
+  const float* mats[2] = {A, B};
+  const int lds[2] = {lda, ldb};
+  const int64_t lx[2] = {ldx, ldxp}, ly[2] = {ldy, ldyp};
+  return kron::strided_call<kron::ModeF32>(2, n, ops, alpha, mats, lds, X, lx, beta, Y, ly, batch, ws, ws_bytes,
+                                           stream);
+}
+
+int kron2d_batched_strided_f64(int n, char opA, char opB, char opX, double alpha, const double* A, int lda,
+                               const double* B, int ldb, const double* X, int64_t ldx, int64_t ldxp, double beta,
+                               double* Y, int64_t ldy, int64_t ldyp, int64_t batch, void* ws, size_t ws_bytes,
+                               hipStream_t stream) {
+  const char ops[3] = {opA, opB, opX};
+  const double* mats[2] = {A, B};
+  const int lds[2] = {lda, ldb};
+  const int64_t lx[2] = {ldx, ldxp}, ly[2] = {ldy, ldyp};
+  return kron::strided_call<kron::ModeF64>(2, n, ops, alpha, mats, lds, X, lx, beta, Y, ly, batch, ws, ws_bytes,
+                                           stream);
+}
+
+int kron3d_batched_strided_f32(int n, char opA, char opB, char opC, float alpha, const float* A, int lda,
+                               const float* B, int ldb, const float* C, int ldc, const float* X, int64_t ldx,
+                               int64_t ldx2, int64_t ldxp, float beta, float* Y, int64_t ldy, int64_t ldy2,
+                               int64_t ldyp, int64_t batch, void* ws, size_t ws_bytes, hipStream_t stream) {
+  const char ops[3] = {opA, opB, opC};
+  const float* mats[3] = {A, B, C};
+  const int lds[3] = {lda, ldb, ldc};
+  const int64_t lx[3] = {ldx, ldx2, ldxp}, ly[3] = {ldy, ldy2, ldyp};
+  return kron::strided_call<kron::ModeF32>(3, n, ops, alpha, mats, lds, X, lx, beta, Y, ly, batch, ws, ws_bytes,
+                                           stream);
+}
+
+int kron3d_batched_strided_f64(int n, char opA, char opB, char opC, double alpha, const double* A, int lda,
+                               const double* B, int ldb, const double* C, int ldc, const double* X, int64_t ldx,
+                               int64_t ldx2, int64_t ldxp, double beta, double* Y, int64_t ldy, int64_t ldy2,
+                               int64_t ldyp, int64_t batch, void* ws, size_t ws_bytes, hipStream_t stream) {
+  const char ops[3] = {opA, opB, opC};
+  const double* mats[3] = {A, B, C};
+  const int lds[3] = {lda, ldb, ldc};
+  const int64_t lx[3] = {ldx, ldx2, ldxp}, ly[3] = {ldy, ldy2, ldyp};
+  return kron::strided_call<kron::ModeF64>(3, n, ops, alpha, mats, lds, X, lx, beta, Y, ly, batch, ws, ws_bytes,
+                                           stream);
+}
+
+}  // extern "C"
