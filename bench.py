@@ -474,9 +474,9 @@ def summarize_trace(trace_dir):
     lines = [
         "# Kernel durations over the whole benchmark run",
         "",
-        "Every `kron` kernel launched by `bench.py` (all modes, the grouped launch, the backward), from one",
-        "rocprofv3 kernel trace. The call counts include the untimed warm-up launches; averages are per dispatch",
-        "under the profiler.",
+        "Every `kron` kernel launched by `bench.py` (all modes, the grouped launch, the extended and strided",
+        "interfaces, the backward), from one rocprofv3 kernel trace. The call counts include the untimed warm-up",
+        "launches; averages are per dispatch under the profiler.",
         "",
         "```",
         "export TMPDIR=/tmp",
@@ -489,7 +489,9 @@ def summarize_trace(trace_dir):
     ]
     for r in rows:
         name = r["Name"].replace("void ", "")
-        if name.endswith(")"):
+        if ">(" in name:
+            name = name[:name.index(">(") + 1]  # template kernel: drop the (possibly cut) parameter list
+        elif name.endswith(")"):
             name = name[:name.rfind("(")]  # drop the parameter list
         lines.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
                      f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} |")
