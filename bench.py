@@ -280,14 +280,14 @@ def measure_ex2d_transx(torch, steps, warmup):
             "sampled_rel_err": float(np.sqrt(num / den))}
 
 
-def measure_strided(torch, steps, warmup):
+def measure_strided(torch, steps, warmup, ld=17):
     """3-D n=16 FP32 through the strided entry point on padded storage:
-    columns of 17 elements (ldx = ldy = 17, ldx2 = 17*16, ldxp = 17*256),
-    beta = 0.  Algorithmic bytes count the elements addressed (2 GiB)."""
+    columns of ld elements (ldx = ldy = ld, ldx2 = ld*16, ldxp = ld*256),
+    beta = 0; ld = 17 takes the element-wise path, ld = 20 the 16-byte
+    vectors.  Algorithmic bytes count the elements addressed (2 GiB)."""
     import paper_1304_7054_amd as kron
     import workloads
     n, batch = 16, workloads.BATCH_3D[16]
-    ld = 17
     ld2, ldp = ld * n, ld * n * n
     g = torch.Generator(device="cuda").manual_seed(workloads.SEED_BASE + 7)
     mats = [torch.rand(n * n, generator=g, device="cuda") * 2 - 1 for _ in range(3)]
@@ -314,7 +314,7 @@ def measure_strided(torch, steps, warmup):
     alg = 2 * batch * n ** 3 * 4
     del mats, X, Y, ws
     torch.cuda.empty_cache()
-    return {"mode": "f32 strided 3-D n=16 (ld 17, padded columns, beta=0)", "batch": batch, "ms": round(kmean, 4),
+    return {"mode": f"f32 strided 3-D n=16 (ld {ld}, padded columns, beta=0)", "batch": batch, "ms": round(kmean, 4),
             "ms_min": round(kmin, 4), "wall_ms_per_step": round(wall, 4),
             "gflops": round(batch * flops_per_op(3, n) / (kmean * 1e-3) / 1e9, 1),
             "gbs": round(alg / (kmean * 1e-3) / 1e9, 1),
@@ -606,8 +606,9 @@ def main():
         others.append(measure_ex2d_transx(torch, args.steps, args.warmup))
         print(f"# measured extended interface 2-D op(X)=T: {others[-1]['gflops']} GFLOP/s", file=sys.stderr,
               flush=True)
-        others.append(measure_strided(torch, args.steps, args.warmup))
-        print(f"# measured strided 3-D: {others[-1]['gflops']} GFLOP/s", file=sys.stderr, flush=True)
+        for ld in (17, 20):
+            others.append(measure_strided(torch, args.steps, args.warmup, ld))
+            print(f"# measured strided 3-D ld {ld}: {others[-1]['gflops']} GFLOP/s", file=sys.stderr, flush=True)
         others.append(measure_backward(torch, args.steps, args.warmup))
         print(f"# measured backward: {others[-1]['ms']} ms", file=sys.stderr, flush=True)
 

@@ -214,10 +214,11 @@ int kron3d_batched_ex_f64(int n, char opA, char opB, char opC, double alpha, con
    library cannot see buffer sizes: the caller guarantees that every address
    the strides reach lies inside its arrays.
    ops, alpha, beta, ws (kron_ex_workspace_size bytes) and stream as for the
-   _ex entry points; opX (2-D) transposes each operand.  Every element is
-   read and written individually, so any stride and any element-aligned
-   address is accepted; contiguous arrays run faster through the _ex entry
-   points.  Returns 0 or -k (argument k invalid; positions beyond 15 are
+   _ex entry points; opX (2-D) transposes each operand.  Any stride and any
+   element-aligned address is accepted: elements are read and written one at
+   a time, except in 3-D with n = 16 when every X and Y stride is a multiple
+   of 4 elements and both bases are 16-byte aligned (then 16-byte vectors).
+   Contiguous arrays run faster through the _ex entry points.  Returns 0 or -k (argument k invalid; positions beyond 15 are
    reported by kron_status_string as "invalid argument"). */
 int kron2d_batched_strided_f32(int n, char opA, char opB, char opX, float alpha, const float* A, int lda,
                                const float* B, int ldb, const float* X, int64_t ldx, int64_t ldxp, float beta,

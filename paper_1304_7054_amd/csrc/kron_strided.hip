@@ -6,7 +6,8 @@
 // The MFMA contractions are those of the dense tiles (Tile2D / Tile3D
 // compute); only the addressing differs.  Every lane computes the element
 // offsets of its slots from the strides at run time (64-bit), reads and
-// writes one element at a time, and keeps the dense kernels' rules: packed
+// writes one element at a time (3-D n = 16 with strides in multiples of 4
+// elements: 16-byte vectors), and keeps the dense kernels' rules: packed
 // tiles for n < 16, dead slots skipped, a tile with a non-finite result redone
 // one operand at a time.
 #include <hip/hip_runtime.h>
@@ -57,7 +58,10 @@ __device__ __forceinline__ void put(T* p, T v, T beta) {
   Mem<T>::store1(p, v);
 }
 
-template <class M, int N, int kDim, bool kBeta, bool kTX>
+// kVec (3-D, n = 16, every stride a multiple of 4 elements, 16-byte aligned
+// bases): the four fast-axis elements of a lane are contiguous and move as
+// one vector, as in the dense kernels.
+template <class M, int N, int kDim, bool kBeta, bool kTX, bool kVec>
 __global__ __launch_bounds__(kBlock) void kron_strided_kernel(const typename M::io_t* __restrict__ A,
                                                               const typename M::io_t* __restrict__ B,
                                                               const typename M::io_t* __restrict__ C,
@@ -67,6 +71,7 @@ __global__ __launch_bounds__(kBlock) void kron_strided_kernel(const typename M::
   using io_t = typename M::io_t;
   using acc_t = typename M::acc_t;
   constexpr int Q = Geo<N>::Q;
+  static_assert(!kVec || (kDim == 3 && N == 16), "vector accesses: 3-D, n = 16");
   const int l = threadIdx.x & 63, L = l & 15, g = l >> 4;
   const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * kBlock) >> 6;
@@ -130,6 +135,11 @@ __global__ __launch_bounds__(kBlock) void kron_strided_kernel(const typename M::
       fy[s] = Site{op * ys.sp + sf.idx + ys.s1 * sL.idx, op, sL.valid && sf.valid};
     }
     auto load = [&](const io_t* Xt, int64_t rem, int only, acc_t (&v)[16]) {
+      if constexpr (kVec) {  // one operand per tile, every slot live
+#pragma unroll
+        for (int b = 0; b < 16; ++b) v[b] = Mem<io_t>::load4(Xt + b * xs.s2 + fx[0].off);
+        return;
+      }
 #pragma unroll
       for (int b = 0; b < 16; ++b) {
         const Slot<N> sb(b);
@@ -144,6 +154,11 @@ __global__ __launch_bounds__(kBlock) void kron_strided_kernel(const typename M::
       }
     };
     auto store = [&](io_t* Yt, int64_t rem, int only, const acc_t (&v)[16]) {
+      if constexpr (kVec) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) put4<kBeta>(Yt + i * ys.s2 + fy[0].off, v[i], beta);
+        return;
+      }
 #pragma unroll
       for (int i = 0; i < 16; ++i) {
         const Slot<N> si(i);
@@ -181,6 +196,10 @@ __global__ __launch_bounds__(kBlock) void kron_strided_kernel(const typename M::
   }
 }
 
+inline bool vec_strides(const Strides& s, const void* base) {
+  return s.s1 % 4 == 0 && s.s2 % 4 == 0 && s.sp % 4 == 0 && reinterpret_cast<uintptr_t>(base) % 16 == 0;
+}
+
 template <class M, int Dim, int N, bool kBeta, bool kTX>
 void launch_strided_k(const typename M::io_t* A, const typename M::io_t* B, const typename M::io_t* C,
                       const typename M::io_t* X, Strides xs, typename M::io_t* Y, Strides ys, int64_t batch,
@@ -188,9 +207,17 @@ void launch_strided_k(const typename M::io_t* A, const typename M::io_t* B, cons
   constexpr int64_t Q = Geo<N>::Q;
   constexpr int64_t ops = Dim == 2 ? Q * Q : Q * Q * Q;
   const int64_t ntiles = (batch + ops - 1) / ops;
-  auto k = kron_strided_kernel<M, N, Dim, kBeta, kTX>;
-  hipLaunchKernelGGL(k, dim3(grid_blocks(ntiles, occupancy_blocks(k), 0)), dim3(kBlock), 0, stream, A, B, C, X, xs,
-                     Y, ys, batch, ntiles, beta);
+  auto run = [&](auto k) {
+    hipLaunchKernelGGL(k, dim3(grid_blocks(ntiles, occupancy_blocks(k), 0)), dim3(kBlock), 0, stream, A, B, C, X,
+                       xs, Y, ys, batch, ntiles, beta);
+  };
+  if constexpr (Dim == 3 && N == 16) {
+    if (vec_strides(xs, X) && vec_strides(ys, Y)) {
+      run(kron_strided_kernel<M, N, Dim, kBeta, kTX, true>);
+      return;
+    }
+  }
+  run(kron_strided_kernel<M, N, Dim, kBeta, kTX, false>);
 }
 
 template <class M, int Dim, int N>

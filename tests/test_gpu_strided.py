@@ -110,6 +110,17 @@ def test_strided3d_padded(mode, n):
 
 
 @pytest.mark.parametrize("mode", ["f32", "f64"])
+@pytest.mark.parametrize("beta", [0.0, 0.5])
+def test_strided3d_vector_path(mode, beta):
+    """3-D n = 16 with every stride a multiple of 4 elements: the 16-byte
+    vector accesses (padded columns, planes and operands)."""
+    _need_gpu()
+    n = 16
+    _run(mode, 3, n, ("T", "N", "N"), 1.25, beta, (n, n, n + 3), (20, 320, 320 * 16 + 8), (16, 260, 260 * 16),
+         23, 950)
+
+
+@pytest.mark.parametrize("mode", ["f32", "f64"])
 @pytest.mark.parametrize("dim", [2, 3])
 def test_strided_dense_layout_matches_ex(mode, dim):
     """Dense strides through the strided kernel give the _ex result (same
