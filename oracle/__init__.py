@@ -51,6 +51,8 @@ class Oracle:
         lib.oracle_kron2d_ex_f64.restype = None
         lib.oracle_kron3d_ex_f64.argtypes = [ctypes.c_int, ch, ch, ch, d, p, p, p, p, d, p, i64]
         lib.oracle_kron3d_ex_f64.restype = None
+        lib.oracle_kron1d_ex_f64.argtypes = [ctypes.c_int, ch, d, p, p, i64, d, p, i64, i64]
+        lib.oracle_kron1d_ex_f64.restype = None
         lib.oracle_num_threads.argtypes = []
         lib.oracle_num_threads.restype = ctypes.c_int
         self.lib = lib
@@ -109,6 +111,20 @@ class Oracle:
         Y = np.array(_prep(Y, dt, batch * n * n), copy=True)
         self.lib.oracle_kron2d_ex_f64(n, opA.encode(), opB.encode(), opX.encode(), alpha, _ptr(A), _ptr(B),
                                       _ptr(X), beta, _ptr(Y), batch)
+        return Y
+
+    def kron1d_ex(self, n, opA, alpha, A, X, beta, Y, batch, ldxp=None, ldyp=None):
+        """y_p <- alpha * op(A) x_p + beta * y_p with x_p at X[p*ldxp:], y_p at
+        Y[p*ldyp:] (default n), in FP64; returns the new Y (a copy)."""
+        dt = np.float64
+        ldxp = n if ldxp is None else int(ldxp)
+        ldyp = n if ldyp is None else int(ldyp)
+        A = _prep(A, dt, n * n)
+        X = np.ascontiguousarray(np.asarray(X, dt).reshape(-1))
+        Y = np.array(np.asarray(Y, dt).reshape(-1), copy=True)
+        if batch > 0 and (X.size < (batch - 1) * ldxp + n or Y.size < (batch - 1) * ldyp + n):
+            raise ValueError("X or Y too small for batch and strides")
+        self.lib.oracle_kron1d_ex_f64(n, opA.encode(), alpha, _ptr(A), _ptr(X), ldxp, beta, _ptr(Y), ldyp, batch)
         return Y
 
     def kron3d_ex(self, n, opA, opB, opC, alpha, A, B, C, X, beta, Y, batch):
@@ -182,6 +198,10 @@ def num_threads():
 
 def kron2d_ex(*args, **kw):
     return default().kron2d_ex(*args, **kw)
+
+
+def kron1d_ex(*args, **kw):
+    return default().kron1d_ex(*args, **kw)
 
 
 def kron3d_ex(*args, **kw):

@@ -175,6 +175,25 @@ ORACLE_API void oracle_kron3d_ex_f64(int n, char opA, char opB, char opC, double
   free(z);
 }
 
+/* 1-D (Section 3's TKRON1, a batched matrix-vector product):
+ *     y_p <- alpha * op(A) x_p + beta * y_p,  p = 0 .. batch-1,
+ * with x_p at X + p*ldxp and y_p at Y + p*ldyp (n elements each).  The sum
+ * runs over j ascending; Y is not read when beta == 0. */
+ORACLE_API void oracle_kron1d_ex_f64(int n, char opA, double alpha, const double* A, const double* X, int64_t ldxp,
+                                     double beta, double* Y, int64_t ldyp, int64_t batch) {
+  double Ao[256];
+  op_matrix(n, opA, A, Ao);
+  for (int64_t p = 0; p < batch; ++p) {
+    const double* x = X + p * ldxp;
+    double* y = Y + p * ldyp;
+    for (int i = 0; i < n; ++i) {
+      double s = 0;
+      for (int j = 0; j < n; ++j) s += Ao[i + n * j] * x[j];
+      y[i] = beta == 0.0 ? alpha * s : alpha * s + beta * y[i];
+    }
+  }
+}
+
 /* ---- gradients (double only) ------------------------------------------ */
 
 static void transpose_n(int n, const double* M, double* Mt) {

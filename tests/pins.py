@@ -410,9 +410,35 @@ def pin_extended_interface(orc, seed=14):
             assert rel(got, 0.75 * base - Y2) < 1e-13, ("2d opX", ops)
 
 
+def pin_tkron1(orc, seed=15):
+    """1-D (Section 3's TKRON1): y_p = alpha op(A) x_p + beta y_p against a
+    numpy matrix product on the explicitly transposed matrix, with padded
+    strides (the gaps keep their values); and, with op = N, alpha = 1,
+    beta = 0, against the 2-D action with an identity first factor on
+    operands made of n consecutive vectors (Y_q = A X_q I^T)."""
+    rng = np.random.default_rng(seed)
+    for n, batch in ((1, 5), (3, 7), (4, 8)):
+        A = rng.uniform(-1, 1, n * n)
+        for op in "NT":
+            Aop = mat(A, n).T if op == "T" else mat(A, n)
+            ldxp, ldyp = n + 2, n + 1
+            X = rng.standard_normal(ldxp * batch)
+            Y = rng.standard_normal(ldyp * batch)
+            got = orc.kron1d_ex(n, op, -1.5, A, X, 0.5, Y, batch, ldxp, ldyp)
+            want = Y.copy()
+            for p in range(batch):
+                want[p * ldyp:p * ldyp + n] = -1.5 * Aop @ X[p * ldxp:p * ldxp + n] + 0.5 * Y[p * ldyp:p * ldyp + n]
+            assert rel(got, want) < 1e-13, ("tkron1", n, op)
+        # n vectors at a time form one 2-D operand whose columns they are
+        Xd = rng.standard_normal(n * n * batch)
+        got = orc.kron1d_ex(n, "N", 1.0, A, Xd, 0.0, np.full(Xd.size, np.nan), n * batch)
+        ident = np.eye(n).reshape(-1)
+        assert rel(got, orc.kron2d(n, ident, A, Xd, batch)) < 1e-13, ("tkron1 vs 2-D", n)
+
+
 ALL_PINS = [
     pin_worked_examples, pin_brute_force, pin_identity, pin_permutation,
     pin_small_integers, pin_mixed_product, pin_adjoint, pin_single_factor,
     pin_rank_one, pin_algorithm1, pin_linearity, pin_batch_independence,
-    pin_gradients, pin_float_accuracy, pin_extended_interface,
+    pin_gradients, pin_float_accuracy, pin_extended_interface, pin_tkron1,
 ]

@@ -45,6 +45,9 @@ MUTATIONS = {
     "ex_ops_swapped": ("  op_matrix(n, opA, A, Ao);\n  op_matrix(n, opB, B, Bo);\n  op_matrix(n, opC, C, Co);",
                        "  op_matrix(n, opB, A, Ao);\n  op_matrix(n, opA, B, Bo);\n  op_matrix(n, opC, C, Co);"),
     "ex_op_x_ignored": ("op_matrix(n, opX, X + p * nn, xo + p * nn);", "op_matrix(n, 'N', X + p * nn, xo + p * nn);"),
+    "tkron1_transpose_ignored": ("  op_matrix(n, opA, A, Ao);\n  for (int64_t p = 0; p < batch; ++p) {\n    const double* x = X + p * ldxp;",
+                                 "  op_matrix(n, 'N', A, Ao);\n  for (int64_t p = 0; p < batch; ++p) {\n    const double* x = X + p * ldxp;"),
+    "tkron1_output_stride": ("    double* y = Y + p * ldyp;", "    double* y = Y + p * ldxp;"),
     "f32_accumulates_in_double": ("DEFINE_KRON2D(oracle_kron2d_f32, float)", "DEFINE_KRON2D(oracle_kron2d_f32_unused, float)\nORACLE_API void oracle_kron2d_f32(int n, const float* A, const float* B, const float* X, float* Y, int64_t batch) { (void)A; (void)B; for (int64_t i = 0; i < batch * n * n; ++i) Y[i] = X[i]; }"),
 }
 
