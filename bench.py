@@ -322,6 +322,39 @@ def measure_strided(torch, steps, warmup, ld=17):
             "sampled_rel_err": float(np.sqrt(num / den))}
 
 
+def measure_tkron1(torch, steps, warmup):
+    """TKRON1 (1-D), n = 16 FP32, 2^24 dense vectors (1 GiB X + 1 GiB Y),
+    alpha = 1, op = N, beta = 0."""
+    import paper_1304_7054_amd as kron
+    import workloads
+    n, batch = 16, 1 << 24
+    g = torch.Generator(device="cuda").manual_seed(workloads.SEED_BASE + 8)
+    A = torch.rand(n * n, generator=g, device="cuda") * 2 - 1
+    X = torch.randn(batch * n, generator=g, device="cuda")
+    Y = torch.empty_like(X)
+    ws = torch.empty(kron.kron_ex_workspace_size(2, n, kron.MODE_F32), dtype=torch.uint8, device="cuda")
+    fn = lambda stream=None: kron.kron1d_batched_f32(n, "N", 1.0, A, n, X, n, 0.0, Y, n, batch, ws, stream)
+    wall, kmean, kmin = time_launches(torch, fn, (), max(10, steps // 2), warmup)
+    torch.cuda.synchronize()
+    Ad = A.double().cpu().numpy().reshape(n, n).T  # column-major
+    rng = np.random.default_rng(8)
+    idx = rng.integers(0, batch, 64)
+    xs = torch.stack([X[q * n:(q + 1) * n] for q in idx]).double().cpu().numpy()
+    ys = torch.stack([Y[q * n:(q + 1) * n] for q in idx]).double().cpu().numpy()
+    import oracle
+    want = oracle.kron1d_ex(n, "N", 1.0, A.double().cpu().numpy(), xs.reshape(-1), 0.0, np.zeros(xs.size), len(idx))
+    err = float(np.linalg.norm(ys.reshape(-1) - want) / np.linalg.norm(want))
+    alg = 2 * X.numel() * 4
+    flops = 2 * n * n * batch
+    del A, X, Y, ws
+    torch.cuda.empty_cache()
+    return {"mode": "f32 TKRON1 1-D n=16 (2^24 vectors)", "batch": batch, "ms": round(kmean, 4),
+            "ms_min": round(kmin, 4), "wall_ms_per_step": round(wall, 4),
+            "gflops": round(flops / (kmean * 1e-3) / 1e9, 1), "gbs": round(alg / (kmean * 1e-3) / 1e9, 1),
+            "hbm_frac": round(alg / (kmean * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "alg_bytes": alg,
+            "sampled_rel_err": err}
+
+
 def measure_backward(torch, steps, warmup):
     """dX + dA + dB + dC of the 3-D n=16 FP32 workload (reads X and dY,
     writes dX: three 1 GiB streams)."""
@@ -609,6 +642,8 @@ def main():
         for ld in (17, 20):
             others.append(measure_strided(torch, args.steps, args.warmup, ld))
             print(f"# measured strided 3-D ld {ld}: {others[-1]['gflops']} GFLOP/s", file=sys.stderr, flush=True)
+        others.append(measure_tkron1(torch, args.steps, args.warmup))
+        print(f"# measured TKRON1: {others[-1]['gflops']} GFLOP/s", file=sys.stderr, flush=True)
         others.append(measure_backward(torch, args.steps, args.warmup))
         print(f"# measured backward: {others[-1]['ms']} ms", file=sys.stderr, flush=True)
 

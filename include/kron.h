@@ -237,6 +237,25 @@ int kron3d_batched_strided_f64(int n, char opA, char opB, char opC, double alpha
                                int64_t ldx2, int64_t ldxp, double beta, double* Y, int64_t ldy, int64_t ldy2,
                                int64_t ldyp, int64_t batch, void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* ---- 1-D: TKRON1 (Section 3), a batched matrix-vector product ------------------- */
+
+/* y_p <- alpha * op(A) x_p + beta * y_p for p = 0 .. batch-1, with x_p the
+   n elements at X + p*ldxp and y_p those at Y + p*ldyp; A is n x n,
+   column-major with leading dimension lda >= n; op 'N'/'n' or 'T'/'t'.
+   ldxp >= 0 (0 repeats one vector), ldyp >= n; X and Y must not overlap.
+   ws: at least kron_ex_workspace_size(2, n, mode) bytes of device memory
+   (alpha * op(A) is written there once per call).  beta == 0 does not read
+   Y.  Each output vector depends only on its own input vector (a NaN stays
+   in its vector).  16 vectors per wavefront and MFMA tile; 16-byte accesses
+   when n = 16, both strides are multiples of 4 elements and X, Y are 16-byte
+   aligned.  Returns 0 or -k (argument k invalid); asynchronous on `stream`. */
+int kron1d_batched_f32(int n, char opA, float alpha, const float* A, int lda, const float* X, int64_t ldxp,
+                       float beta, float* Y, int64_t ldyp, int64_t batch, void* ws, size_t ws_bytes,
+                       hipStream_t stream);
+int kron1d_batched_f64(int n, char opA, double alpha, const double* A, int lda, const double* X, int64_t ldxp,
+                       double beta, double* Y, int64_t ldyp, int64_t batch, void* ws, size_t ws_bytes,
+                       hipStream_t stream);
+
 /* ---- backward ---------------------------------------------------------------- */
 
 /* Gradients of L = sum_p <dY_p, Y_p> for the forward actions above (the

@@ -22,6 +22,8 @@ from ._binding import (  # noqa: F401
     kron3d_batched_ex_f32,
     kron3d_batched_ex_f64,
     kron_ex_workspace_size,
+    kron1d_batched_f32,
+    kron1d_batched_f64,
     kron2d_batched_strided_f32,
     kron2d_batched_strided_f64,
     kron3d_batched_strided_f32,

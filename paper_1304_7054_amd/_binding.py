@@ -59,6 +59,8 @@ SIGNATURES = {
     "kron2d_batched_ex_f64": "icccdpppdplpzS",
     "kron3d_batched_ex_f32": "icccfppppfplpzS",
     "kron3d_batched_ex_f64": "icccdppppdplpzS",
+    "kron1d_batched_f32": "icfpiplfpllpzS",
+    "kron1d_batched_f64": "icdpipldpllpzS",
     "kron2d_batched_strided_f32": "icccfpipipllfplllpzS",
     "kron2d_batched_strided_f64": "icccdpipiplldplllpzS",
     "kron3d_batched_strided_f32": "icccfpipipiplllfpllllpzS",
@@ -406,6 +408,43 @@ def kron3d_batched_strided_f64(n, opA, opB, opC, alpha, A, lda, B, ldb, C, ldc, 
     return _strided_call("kron3d_batched_strided_f64", 3, torch.float64, MODE_F64, n, (opA, opB, opC),
                          float(alpha), (A, B, C), (lda, ldb, ldc), X, (ldx, ldx2, ldxp), float(beta), Y,
                          (ldy, ldy2, ldyp), batch, ws, stream)
+
+
+def _tkron1_call(name, dtype, mode, n, opA, alpha, A, lda, X, ldxp, beta, Y, ldyp, batch, ws, stream):
+    n, batch, lda, ldxp, ldyp = int(n), int(batch), int(lda), int(ldxp), int(ldyp)
+    if not 1 <= n <= 16:
+        raise ValueError(f"n must be in 1..16, got {n}")
+    if batch < 0:
+        raise ValueError("batch must be >= 0")
+    if lda < n or ldxp < 0 or ldyp < n:
+        raise ValueError("need lda >= n, ldxp >= 0, ldyp >= n")
+    opc = _op_char(opA, "opA")
+    pa = _arr(A, dtype, (n - 1) * lda + n, "A")
+    ex = (batch - 1) * ldxp + n if batch > 0 else 0
+    ey = (batch - 1) * ldyp + n if batch > 0 else 0
+    px = _arr(X, dtype, ex, "X")
+    py = _arr(Y, dtype, ey, "Y")
+    if batch > 0:
+        esz = X.element_size()
+        x0, y0 = X.data_ptr(), Y.data_ptr()
+        if x0 < y0 + ey * esz and y0 < x0 + ex * esz:
+            raise ValueError("X and Y must not overlap")
+    need = kron_ex_workspace_size(2, n, mode)
+    if ws is None:
+        ws = torch.empty(need, dtype=torch.uint8, device=Y.device)
+    pw = _arr(ws, torch.uint8, need, "workspace")
+    return _call(name, n, opc, alpha, pa, lda, px, ldxp, beta, py, ldyp, batch, pw, ws.numel(), _stream(stream))
+
+
+def kron1d_batched_f32(n, opA, alpha, A, lda, X, ldxp, beta, Y, ldyp, batch, ws=None, stream=None):
+    """TKRON1: y_p = alpha op(A) x_p + beta y_p, x_p at X[p*ldxp:], FP32 (see include/kron.h)."""
+    return _tkron1_call("kron1d_batched_f32", torch.float32, MODE_F32, n, opA, float(alpha), A, lda, X, ldxp,
+                        float(beta), Y, ldyp, batch, ws, stream)
+
+
+def kron1d_batched_f64(n, opA, alpha, A, lda, X, ldxp, beta, Y, ldyp, batch, ws=None, stream=None):
+    return _tkron1_call("kron1d_batched_f64", torch.float64, MODE_F64, n, opA, float(alpha), A, lda, X, ldxp,
+                        float(beta), Y, ldyp, batch, ws, stream)
 
 
 def _groups_array(groups):

@@ -252,7 +252,115 @@ int launch_strided(int n, const typename M::io_t* A, const typename M::io_t* B, 
   }
 }
 
+// ---- 1-D: TKRON1, y_p <- alpha op(A) x_p + beta y_p ---------------------------
+//
+// One tile is 16 vectors: D = Aop * [x_p .. x_p+15] on the 16x16 MFMA, with
+// Aop = alpha op(A) padded to 16 x 16 with zeros.  Lane (L, g) supplies row L
+// of Aop and column L (vector p + L) of the block at contraction slots
+// 4g + s, and receives rows drow(g, r) of that column (FP64: regrouped to
+// 4g + r).  Each output column sees only its own vector, so a NaN stays in
+// its vector.  kVec (n = 16, strides multiples of 4 elements, 16-byte aligned
+// bases): one 16-byte load and store per lane and tile.
+template <class M, bool kVec, bool kBeta>
+__global__ __launch_bounds__(kBlock) void kron1d_kernel(int n, const typename M::io_t* __restrict__ Aop,
+                                                        const typename M::io_t* __restrict__ X, int64_t ldxp,
+                                                        typename M::io_t* __restrict__ Y, int64_t ldyp,
+                                                        int64_t batch, int64_t ntiles, typename M::io_t beta) {
+  using io_t = typename M::io_t;
+  using acc_t = typename M::acc_t;
+  const int l = threadIdx.x & 63, L = l & 15, g = l >> 4;
+  const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * kBlock) >> 6;
+  io_t a[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int k = 4 * g + s;
+    a[s] = (L < n && k < n) ? Aop[L + n * k] : io_t(0);
+  }
+  for (int64_t t = wave; t < ntiles; t += nwaves) {
+    const int64_t p = t * 16 + L;
+    const bool live = p < batch;
+    acc_t x;
+    if constexpr (kVec) {
+      x = live ? Mem<io_t>::load4(X + p * ldxp + 4 * g) : acc_t{0, 0, 0, 0};
+    } else {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int k = 4 * g + s;
+        x[s] = (live && k < n) ? Mem<io_t>::load1(X + p * ldxp + k) : io_t(0);
+      }
+    }
+    acc_t y = {0, 0, 0, 0};
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      if constexpr (sizeof(io_t) == 8) y = mfma_f64(a[s], x[s], y);
+      else y = mfma_f32(a[s], x[s], y);
+    }
+    if constexpr (M::drow(0, 1) != 1) transpose_groups_regs(y);  // rows 4g + r
+    if constexpr (kVec) {
+      if (live) put4<kBeta>(Y + p * ldyp + 4 * g, y, beta);
+    } else {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 4 * g + r;
+        if (live && i < n) put<kBeta>(Y + p * ldyp + i, y[r], beta);
+      }
+    }
+  }
+}
+
+// alpha op(A) with leading dimension lda, written dense
+template <typename T>
+__global__ __launch_bounds__(256) void prepare_tkron1_kernel(int n, const T* __restrict__ A, int lda, int trans,
+                                                             T alpha, T* __restrict__ out) {
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+    const int i = e % n, j = e / n;
+    out[e] = alpha * (trans ? A[j + (int64_t)lda * i] : A[i + (int64_t)lda * j]);
+  }
+}
+
 int op_code(char op) { return (op == 'N' || op == 'n') ? 0 : (op == 'T' || op == 't') ? 1 : -1; }
+
+// Positions: n 1, opA 2, alpha 3, A 4, lda 5, X 6, ldxp 7, beta 8, Y 9,
+// ldyp 10, batch 11, ws 12, ws_bytes 13.
+template <class M>
+int tkron1_call(int n, char opA, typename M::io_t alpha, const typename M::io_t* A, int lda,
+                const typename M::io_t* X, int64_t ldxp, typename M::io_t beta, typename M::io_t* Y, int64_t ldyp,
+                int64_t batch, void* ws, size_t ws_bytes, hipStream_t stream) {
+  using T = typename M::io_t;
+  if (n < 1 || n > KRON_MAX_N) return -1;
+  const int trans = op_code(opA);
+  if (trans < 0) return -2;
+  if (!A) return -4;
+  if (lda < n) return -5;
+  if (!X || reinterpret_cast<uintptr_t>(X) % sizeof(T) != 0) return -6;
+  if (ldxp < 0) return -7;
+  if (!Y || reinterpret_cast<uintptr_t>(Y) % sizeof(T) != 0 || (const void*)Y == (const void*)X) return -9;
+  if (ldyp < n) return -10;
+  if (batch < 0) return -11;
+  if (batch == 0) return 0;
+  if (!ws || reinterpret_cast<uintptr_t>(ws) % sizeof(T) != 0) return -12;
+  if (ws_bytes < (size_t)n * n * sizeof(T)) return -13;
+  T* P = static_cast<T*>(ws);
+  hipLaunchKernelGGL(prepare_tkron1_kernel<T>, dim3(1), dim3(256), 0, stream, n, A, lda, trans, alpha, P);
+  const int64_t ntiles = (batch + 15) / 16;
+  const bool vec = n == 16 && ldxp % 4 == 0 && ldyp % 4 == 0 && reinterpret_cast<uintptr_t>(X) % 16 == 0 &&
+                   reinterpret_cast<uintptr_t>(Y) % 16 == 0;
+  const bool has_beta = beta != T(0);
+  auto run = [&](auto k) {
+    hipLaunchKernelGGL(k, dim3(grid_blocks(ntiles, occupancy_blocks(k), 0)), dim3(kBlock), 0, stream, n, P, X, ldxp,
+                       Y, ldyp, batch, ntiles, beta);
+  };
+  if (vec) {
+    if (has_beta) run(kron1d_kernel<M, true, true>);
+    else run(kron1d_kernel<M, true, false>);
+  } else {
+    if (has_beta) run(kron1d_kernel<M, false, true>);
+    else run(kron1d_kernel<M, false, false>);
+  }
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? 0 : (int)e;
+}
 
 // Argument checks and launches shared by the four entry points.  The
 // argument positions of the C signatures: n 1, the ops 2-4, alpha 5, then
@@ -312,6 +420,18 @@ int strided_call(int dim, int n, const char* ops, typename M::io_t alpha, const 
 }  // namespace kron
 
 extern "C" {
+
+int kron1d_batched_f32(int n, char opA, float alpha, const float* A, int lda, const float* X, int64_t ldxp,
+                       float beta, float* Y, int64_t ldyp, int64_t batch, void* ws, size_t ws_bytes,
+                       hipStream_t stream) {
+  return kron::tkron1_call<kron::ModeF32>(n, opA, alpha, A, lda, X, ldxp, beta, Y, ldyp, batch, ws, ws_bytes, stream);
+}
+
+int kron1d_batched_f64(int n, char opA, double alpha, const double* A, int lda, const double* X, int64_t ldxp,
+                       double beta, double* Y, int64_t ldyp, int64_t batch, void* ws, size_t ws_bytes,
+                       hipStream_t stream) {
+  return kron::tkron1_call<kron::ModeF64>(n, opA, alpha, A, lda, X, ldxp, beta, Y, ldyp, batch, ws, ws_bytes, stream);
+}
 
 int kron2d_batched_strided_f32(int n, char opA, char opB, char opX, float alpha, const float* A, int lda,
                                const float* B, int ldb, const float* X, int64_t ldx, int64_t ldxp, float beta,
