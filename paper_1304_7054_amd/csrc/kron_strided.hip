@@ -259,8 +259,9 @@ int launch_strided(int n, const typename M::io_t* A, const typename M::io_t* B, 
 // of Aop and column L (vector p + L) of the block at contraction slots
 // 4g + s, and receives rows drow(g, r) of that column (FP64: regrouped to
 // 4g + r).  Each output column sees only its own vector, so a NaN stays in
-// its vector.  kVec (n = 16, strides multiples of 4 elements, 16-byte aligned
-// bases): one 16-byte load and store per lane and tile.
+// its vector.  Four tiles are in flight per wavefront.  kVec (n = 16, strides
+// multiples of 4 elements, 16-byte aligned bases): one 16-byte load and store
+// per lane and tile.
 template <class M, bool kVec, bool kBeta>
 __global__ __launch_bounds__(kBlock) void kron1d_kernel(int n, const typename M::io_t* __restrict__ Aop,
                                                         const typename M::io_t* __restrict__ X, int64_t ldxp,
@@ -277,33 +278,42 @@ __global__ __launch_bounds__(kBlock) void kron1d_kernel(int n, const typename M:
     const int k = 4 * g + s;
     a[s] = (L < n && k < n) ? Aop[L + n * k] : io_t(0);
   }
-  for (int64_t t = wave; t < ntiles; t += nwaves) {
-    const int64_t p = t * 16 + L;
-    const bool live = p < batch;
-    acc_t x;
-    if constexpr (kVec) {
-      x = live ? Mem<io_t>::load4(X + p * ldxp + 4 * g) : acc_t{0, 0, 0, 0};
-    } else {
+  constexpr int kTiles = 4;  // tiles in flight per wavefront: all loads, then the products, then the stores
+  for (int64_t base = wave * kTiles; base < ntiles; base += nwaves * kTiles) {
+    acc_t x[kTiles];
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int k = 4 * g + s;
-        x[s] = (live && k < n) ? Mem<io_t>::load1(X + p * ldxp + k) : io_t(0);
+    for (int j = 0; j < kTiles; ++j) {
+      const int64_t p = (base + j) * 16 + L;
+      const bool live = p < batch;
+      if constexpr (kVec) {
+        x[j] = live ? Mem<io_t>::load4(X + p * ldxp + 4 * g) : acc_t{0, 0, 0, 0};
+      } else {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const int k = 4 * g + s;
+          x[j][s] = (live && k < n) ? Mem<io_t>::load1(X + p * ldxp + k) : io_t(0);
+        }
       }
     }
-    acc_t y = {0, 0, 0, 0};
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      if constexpr (sizeof(io_t) == 8) y = mfma_f64(a[s], x[s], y);
-      else y = mfma_f32(a[s], x[s], y);
-    }
-    if constexpr (M::drow(0, 1) != 1) transpose_groups_regs(y);  // rows 4g + r
-    if constexpr (kVec) {
-      if (live) put4<kBeta>(Y + p * ldyp + 4 * g, y, beta);
-    } else {
+    for (int j = 0; j < kTiles; ++j) {
+      const int64_t p = (base + j) * 16 + L;
+      const bool live = p < batch;
+      acc_t y = {0, 0, 0, 0};
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = 4 * g + r;
-        if (live && i < n) put<kBeta>(Y + p * ldyp + i, y[r], beta);
+      for (int s = 0; s < 4; ++s) {
+        if constexpr (sizeof(io_t) == 8) y = mfma_f64(a[s], x[j][s], y);
+        else y = mfma_f32(a[s], x[j][s], y);
+      }
+      if constexpr (M::drow(0, 1) != 1) transpose_groups_regs(y);  // rows 4g + r
+      if constexpr (kVec) {
+        if (live) put4<kBeta>(Y + p * ldyp + 4 * g, y, beta);
+      } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = 4 * g + r;
+          if (live && i < n) put<kBeta>(Y + p * ldyp + i, y[r], beta);
+        }
       }
     }
   }
@@ -348,8 +358,8 @@ int tkron1_call(int n, char opA, typename M::io_t alpha, const typename M::io_t*
                    reinterpret_cast<uintptr_t>(Y) % 16 == 0;
   const bool has_beta = beta != T(0);
   auto run = [&](auto k) {
-    hipLaunchKernelGGL(k, dim3(grid_blocks(ntiles, occupancy_blocks(k), 0)), dim3(kBlock), 0, stream, n, P, X, ldxp,
-                       Y, ldyp, batch, ntiles, beta);
+    hipLaunchKernelGGL(k, dim3(grid_blocks((ntiles + 3) / 4, occupancy_blocks(k), 0)), dim3(kBlock), 0, stream, n, P,
+                       X, ldxp, Y, ldyp, batch, ntiles, beta);
   };
   if (vec) {
     if (has_beta) run(kron1d_kernel<M, true, true>);
