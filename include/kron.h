@@ -13,7 +13,10 @@
  *     (a, b, c) stored at a*n*n + b*n + c:
  *       Y_p(i, j, k) = sum_{a,b,c} A(i, a) B(j, b) C(k, c) X_p(a, b, c).
  *   Both are the batched update of Section 2.2 with alpha = 1, beta = 0 and
- *   op = N everywhere (the setting the paper measures in Section 5).
+ *   op = N everywhere (the setting the paper measures in Section 5).  The
+ *   general update (alpha, beta, op on the factors and on 2-D operands,
+ *   leading dimensions) and the 1-D TKRON1 of Section 3 have entry points
+ *   of their own further below.
  *
  * Layout (Section 3): every matrix is n x n column-major with leading
  * dimension n (element (i, j) at i + n*j); operands are packed back to back
@@ -29,8 +32,8 @@
  * `stream` (0 = the null stream) unless noted.
  *
  * Aliasing: X and Y must not overlap; X == Y is rejected, partial overlap is
- * undefined.  Y is write-only (beta = 0): its previous contents, NaN
- * included, never reach the result.
+ * undefined.  In the plain entry points Y is write-only (beta = 0): its
+ * previous contents, NaN included, never reach the result.
  *
  * Return value: 0 on success; -k when argument k (1-based) is invalid;
  * a positive hipError_t when a HIP call fails.  batch == 0 returns 0 and
