@@ -322,6 +322,46 @@ def measure_strided(torch, steps, warmup, ld=17):
             "sampled_rel_err": float(np.sqrt(num / den))}
 
 
+def measure_strided2d(torch, steps, warmup, ld=17):
+    """2-D n=16 FP32 through the strided entry point on padded storage:
+    columns of ld elements (ldx = ldy = ld, ldxp = ld*16), beta = 0,
+    262,144 arrays (1 GiB addressed in X and in Y)."""
+    import paper_1304_7054_amd as kron
+    import workloads
+    n, batch = 16, workloads.BATCH_2D[16]
+    ldp = ld * n
+    g = torch.Generator(device="cuda").manual_seed(workloads.SEED_BASE + 9)
+    mats = [torch.rand(n * n, generator=g, device="cuda") * 2 - 1 for _ in range(2)]
+    X = torch.randn(ldp * batch, generator=g, device="cuda")
+    Y = torch.empty_like(X)
+    ws = torch.empty(kron.kron_ex_workspace_size(2, n, kron.MODE_F32), dtype=torch.uint8, device="cuda")
+    fn = lambda stream=None: kron.kron2d_batched_strided_f32(n, "N", "N", "N", 1.0, mats[0], n, mats[1], n, X, ld,
+                                                             ldp, 0.0, Y, ld, ldp, batch, ws, stream)
+    wall, kmean, kmin = time_launches(torch, fn, (), max(10, steps // 2), warmup)
+    torch.cuda.synchronize()
+    import oracle
+    rng = np.random.default_rng(9)
+    hm = [m.double().cpu().numpy() for m in mats]
+    r = np.arange(n)
+    sub = (r[None, :] + ld * r[:, None]).reshape(-1)
+    num = den = 0.0
+    for q in rng.integers(0, batch, 16):
+        x = X[q * ldp:(q + 1) * ldp].double().cpu().numpy()[sub]
+        want = oracle.kron2d(n, *hm, x, 1)
+        got = Y[q * ldp:(q + 1) * ldp].double().cpu().numpy()[sub]
+        num += float(np.sum((got - want) ** 2))
+        den += float(np.sum(want ** 2))
+    alg = 2 * batch * n * n * 4
+    del mats, X, Y, ws
+    torch.cuda.empty_cache()
+    return {"mode": f"f32 strided 2-D n=16 (ld {ld}, padded columns, beta=0)", "batch": batch, "ms": round(kmean, 4),
+            "ms_min": round(kmin, 4), "wall_ms_per_step": round(wall, 4),
+            "gflops": round(batch * flops_per_op(2, n) / (kmean * 1e-3) / 1e9, 1),
+            "gbs": round(alg / (kmean * 1e-3) / 1e9, 1),
+            "hbm_frac": round(alg / (kmean * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "alg_bytes": alg,
+            "sampled_rel_err": float(np.sqrt(num / den))}
+
+
 def measure_tkron1(torch, steps, warmup):
     """TKRON1 (1-D), n = 16 FP32, 2^24 dense vectors (1 GiB X + 1 GiB Y),
     alpha = 1, op = N, beta = 0."""
@@ -642,6 +682,8 @@ def main():
         for ld in (17, 20):
             others.append(measure_strided(torch, args.steps, args.warmup, ld))
             print(f"# measured strided 3-D ld {ld}: {others[-1]['gflops']} GFLOP/s", file=sys.stderr, flush=True)
+        others.append(measure_strided2d(torch, args.steps, args.warmup))
+        print(f"# measured strided 2-D: {others[-1]['gflops']} GFLOP/s", file=sys.stderr, flush=True)
         others.append(measure_tkron1(torch, args.steps, args.warmup))
         print(f"# measured TKRON1: {others[-1]['gflops']} GFLOP/s", file=sys.stderr, flush=True)
         others.append(measure_backward(torch, args.steps, args.warmup))

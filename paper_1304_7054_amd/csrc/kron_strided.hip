@@ -107,16 +107,29 @@ __global__ __launch_bounds__(kBlock) void kron_strided_kernel(const typename M::
       for (int r = 0; r < 4; ++r)
         if (out[r].valid && out[r].op < rem && (only < 0 || out[r].op == only)) put<kBeta>(Yt + out[r].off, y[r], beta);
     };
-    for (int64_t t = wave; t < ntiles; t += nwaves) {
-      const io_t* Xt = X + t * kOps * xs.sp;
-      io_t* Yt = Y + t * kOps * ys.sp;
-      const int64_t rem = batch - t * kOps;
-      acc_t y = tile.compute(load(Xt, rem, -1));
-      if (kOps > 1 && __any(!all_finite(y))) {
-        const int last = rem < kOps ? (int)rem : kOps;
-        for (int o = 0; o < last; ++o) store(Yt, rem, o, tile.compute(load(Xt, rem, o)));
-      } else {
-        store(Yt, rem, -1, y);
+    // four tiles in flight per wavefront: their loads, then products and stores
+    constexpr int kTiles = 4;
+    for (int64_t base = wave * kTiles; base < ntiles; base += nwaves * kTiles) {
+      acc_t x[kTiles];
+#pragma unroll
+      for (int j = 0; j < kTiles; ++j) {
+        const int64_t t = base + j;
+        x[j] = t < ntiles ? load(X + t * kOps * xs.sp, batch - t * kOps, -1) : acc_t{0, 0, 0, 0};
+      }
+#pragma unroll
+      for (int j = 0; j < kTiles; ++j) {
+        const int64_t t = base + j;
+        if (t >= ntiles) continue;
+        const io_t* Xt = X + t * kOps * xs.sp;
+        io_t* Yt = Y + t * kOps * ys.sp;
+        const int64_t rem = batch - t * kOps;
+        const acc_t y = tile.compute(x[j]);
+        if (kOps > 1 && __any(!all_finite(y))) {
+          const int last = rem < kOps ? (int)rem : kOps;
+          for (int o = 0; o < last; ++o) store(Yt, rem, o, tile.compute(load(Xt, rem, o)));
+        } else {
+          store(Yt, rem, -1, y);
+        }
       }
     }
   } else {
@@ -207,8 +220,9 @@ void launch_strided_k(const typename M::io_t* A, const typename M::io_t* B, cons
   constexpr int64_t Q = Geo<N>::Q;
   constexpr int64_t ops = Dim == 2 ? Q * Q : Q * Q * Q;
   const int64_t ntiles = (batch + ops - 1) / ops;
+  const int64_t waves = Dim == 2 ? (ntiles + 3) / 4 : ntiles;  // 2-D: four tiles per wavefront step
   auto run = [&](auto k) {
-    hipLaunchKernelGGL(k, dim3(grid_blocks(ntiles, occupancy_blocks(k), 0)), dim3(kBlock), 0, stream, A, B, C, X,
+    hipLaunchKernelGGL(k, dim3(grid_blocks(waves, occupancy_blocks(k), 0)), dim3(kBlock), 0, stream, A, B, C, X,
                        xs, Y, ys, batch, ntiles, beta);
   };
   if constexpr (Dim == 3 && N == 16) {
