@@ -203,7 +203,13 @@ int kron3d_batched_ex_f64(int n, char opA, char opB, char opC, double alpha, con
 /* ---- Section 3's interface with leading dimensions ------------------------------ */
 
 /* The extended update above on strided storage, with the argument layout of
-   the paper's TKRON2 / TKRON3 (Section 3) restricted to square n x n factors:
+   the paper's TKRON2 / TKRON3 (Section 3) restricted to square n x n factors.
+   The factor roles keep this library's convention, not TKRON's: the first
+   factor argument acts on the slowest operand index and the last one on the
+   fastest, so in the paper's notation these calls compute
+   K(op(C), op(B), op(A)) in 3-D and K(op(B), op(A)) in 2-D (TKRON names A the
+   factor of the first, fastest index).  The kron{2,3}d_tkron_* entry points
+   below take TKRON's roles and rectangular factors.
      factor M (A, B, C): column-major with leading dimension ld >= n;
      2-D operand p: X_p(l, m) at X[l + ldx*m + ldxp*p], result likewise in Y
        with ldy, ldyp;

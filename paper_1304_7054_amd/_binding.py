@@ -144,6 +144,19 @@ def _stream(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
+def _scratch(need, device, stream):
+    """A workspace the binding allocates on the caller's behalf.  The caching
+    allocator tracks the current stream; when the kernels run on another
+    stream the block is recorded on that stream too, so it is not handed to
+    a new tensor before those kernels have read it."""
+    ws = torch.empty(need, dtype=torch.uint8, device=device)
+    if stream is not None:
+        ts = torch.cuda.ExternalStream(stream, device=device) if isinstance(stream, int) else stream
+        if ts.cuda_stream != torch.cuda.current_stream(device).cuda_stream:
+            ws.record_stream(ts)
+    return ws
+
+
 def _arr(t, dtype, min_numel, what):
     if t is None:
         return None
@@ -309,7 +322,7 @@ def _ex_call(name, dim, dtype, mode, n, ops, alpha, mats, X, beta, Y, batch, ws,
         raise ValueError("X and Y must not overlap")
     need = kron_ex_workspace_size(dim, n, mode)
     if ws is None:
-        ws = torch.empty(need, dtype=torch.uint8, device=X.device)
+        ws = _scratch(need, X.device, stream)
     pw = _arr(ws, torch.uint8, need, "workspace")
     return _call(name, n, *opc, alpha, *ptrs, px, beta, py, batch, pw, ws.numel(), _stream(stream))
 
@@ -374,7 +387,7 @@ def _strided_call(name, dim, dtype, mode, n, ops, alpha, mats, lds, X, ldx, beta
             raise ValueError("X and Y must not overlap")
     need = kron_ex_workspace_size(dim, n, mode)
     if ws is None:
-        ws = torch.empty(need, dtype=torch.uint8, device=Y.device)
+        ws = _scratch(need, Y.device, stream)
     pw = _arr(ws, torch.uint8, need, "workspace")
     return _call(name, n, *opc, alpha, *ptrs, px, *ldx, beta, py, *ldy, batch, pw, ws.numel(), _stream(stream))
 
@@ -431,7 +444,7 @@ def _tkron1_call(name, dtype, mode, n, opA, alpha, A, lda, X, ldxp, beta, Y, ldy
             raise ValueError("X and Y must not overlap")
     need = kron_ex_workspace_size(2, n, mode)
     if ws is None:
-        ws = torch.empty(need, dtype=torch.uint8, device=Y.device)
+        ws = _scratch(need, Y.device, stream)
     pw = _arr(ws, torch.uint8, need, "workspace")
     return _call(name, n, opc, alpha, pa, lda, px, ldxp, beta, py, ldyp, batch, pw, ws.numel(), _stream(stream))
 

@@ -12,7 +12,9 @@ vec(Y_p) = (A kron B (kron C)) vec(X_p), the library's C ABI convention; for
 wrapper gives the kernels the column-major copies of the n x n factors (the
 paper's transpose-once, Section 2.2); all batch work runs in libkron.
 Backward: dX from the transposed action, dA/dB/dC batch-reduced by the
-factor-gradient kernels (deterministic).
+factor-gradient kernels (deterministic).  The backward is first order only:
+its kernels write plain tensors with no graph, so asking for a second
+derivative through it raises instead of silently treating it as constant.
 """
 import torch
 
@@ -69,6 +71,7 @@ class KronFn(torch.autograd.Function):
         return Y
 
     @staticmethod
+    @torch.autograd.function.once_differentiable
     def backward(ctx, dY):
         X, *cm = ctx.saved_tensors
         dim, n = ctx.dim, ctx.n

@@ -4,8 +4,8 @@ Each ``pin_*`` function takes an oracle object (``oracle.Oracle``) and raises
 AssertionError when the oracle disagrees with a value that does not come from
 the oracle's own arithmetic: a hand-derived worked example, an explicitly
 formed Kronecker matrix (numpy.kron), an algebraic identity, a closed form, a
-reduction to a numpy library routine, the paper's Algorithm 1 restated in
-numpy, or central finite differences.  The same functions are run against
+reduction to a numpy library routine, the triple summation of Section 2.1 as one
+numpy einsum, or central finite differences.  The same functions are run against
 deliberately altered builds of the oracle to show that they catch mistakes.
 
 Conventions (shared with the oracle): matrices are column-major flat arrays;
@@ -243,35 +243,25 @@ def pin_rank_one(orc, seed=8):
         assert rel(orc.kron3d(n, A, B, C, X3, 1), want3) < 1e-14, ("rank-1 3-D", n)
 
 
-# ---- P9: the paper's Algorithm 1 as an independent 3-D formulation ---------
+# ---- P9: the triple summation of Section 2.1 as one contraction -------------
 
-def algorithm1(P, Q, R, X):
-    """Algorithm 1 of Section 4 restated with numpy on one column-major array X
-    of shape (na, nb, nc): first every slice X(:,:,N) becomes P X(:,:,N) Q^T in
-    tmp, then for every J the matrix tmp(:,J,:) is multiplied by R^T on the
-    right and stored as Y(:,J,:).  Returns Y with vec(Y) = (R kron Q kron P) vec(X)."""
-    ma, mb, mc = P.shape[0], Q.shape[0], R.shape[0]
-    nc = X.shape[2]
-    tmp = np.zeros((ma, mb, nc))
-    for N in range(nc):
-        tmp[:, :, N] = P @ X[:, :, N] @ Q.T
-    Y = np.zeros((ma, mb, mc))
-    for J in range(mb):
-        Y[:, J, :] = tmp[:, J, :] @ R.T
-    return Y
+def triple_sum(P, Q, R, X):
+    """Section 2.1's triple summation Y_ijk = sum_{l,m,n} P_il Q_jm R_kn X_lmn on
+    one array X indexed (l, m, n), written as a single einsum: no mode order,
+    no intermediate array."""
+    return np.einsum("il,jm,kn,lmn->ijk", P, Q, R, X)
 
 
-def pin_algorithm1(orc, seed=9):
+def pin_triple_sum(orc, seed=9):
     rng = np.random.default_rng(seed)
     for n in (2, 5, 10, 16):
         A, B, C = rand_mats(rng, n, 3)
         Xflat = rng.standard_normal(n ** 3)
-        # memory index a*n^2 + b*n + c is the column-major index of (c, b, a)
-        Xcm = Xflat.reshape(n, n, n, order="C").transpose(2, 1, 0)   # Xcm[c, b, a]
-        Ycm = algorithm1(mat(C, n), mat(B, n), mat(A, n), Xcm)
-        want = Ycm.transpose(2, 1, 0).reshape(-1)
+        # memory index a*n^2 + b*n + c: the library's A acts on a, C on c
+        Xt = Xflat.reshape(n, n, n)
+        want = triple_sum(mat(A, n), mat(B, n), mat(C, n), Xt).reshape(-1)
         got = orc.kron3d(n, A, B, C, Xflat, 1)
-        assert rel(got, want) < 1e-14, ("Algorithm 1", n, rel(got, want))
+        assert rel(got, want) < 1e-14, ("triple summation", n, rel(got, want))
 
 
 # ---- P10: linearity ---------------------------------------------------------
@@ -439,6 +429,6 @@ def pin_tkron1(orc, seed=15):
 ALL_PINS = [
     pin_worked_examples, pin_brute_force, pin_identity, pin_permutation,
     pin_small_integers, pin_mixed_product, pin_adjoint, pin_single_factor,
-    pin_rank_one, pin_algorithm1, pin_linearity, pin_batch_independence,
+    pin_rank_one, pin_triple_sum, pin_linearity, pin_batch_independence,
     pin_gradients, pin_float_accuracy, pin_extended_interface, pin_tkron1,
 ]

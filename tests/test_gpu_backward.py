@@ -141,6 +141,20 @@ def test_autograd_matches_torch_reference_fp32(dim, n):
         assert _rel(m.grad.cpu(), r.grad) <= 1e-5
 
 
+def test_second_derivative_raises():
+    """The hand-written backward is first order: a double backward through it
+    must raise rather than treat its outputs as constants."""
+    _need_gpu()
+    from paper_1304_7054_amd.autograd import kron3d
+    n, batch = 4, 3
+    X = torch.randn((batch, n, n, n), device=DEV, requires_grad=True)
+    mats = [torch.randn(n, n, device=DEV, requires_grad=True) for _ in range(3)]
+    Y = kron3d(X, *mats)
+    (gx,) = torch.autograd.grad(Y.square().sum(), X, create_graph=True)
+    with pytest.raises(RuntimeError):
+        gx.sum().backward()
+
+
 def test_mixed_shapes_finite_differences_fp64():
     """The mixed workload's group shapes (a few (dim, n) groups, FP64), with
     gradients checked by central differences (h = 1e-3) of the library's own

@@ -222,3 +222,44 @@ def test_ex_rejections():
     X2, Y2 = X[: batch * n * n], Y[: batch * n * n]
     assert L.kron2d_batched_ex_f32(n, b"N", b"N", b"Q", 1.0, p[0], p[1], X2.data_ptr(), 0.0, Y2.data_ptr(), batch,
                                    ws.data_ptr(), ws.numel(), s) == -4
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_internal_workspace_on_side_stream(dim):
+    """The binding allocates the factor workspace itself when none is given.
+    With the kernels on a side stream, a tensor allocated on the current
+    stream right after the call must not reuse that block before the side
+    stream's kernels have read it: the result still matches the oracle."""
+    _need_gpu()
+    n, batch = 16, 4096
+    rng = np.random.default_rng(77 + dim)
+    mats = [rng.uniform(-1, 1, n * n) for _ in range(dim)]
+    X = rng.standard_normal(batch * n ** dim)
+    tm = [torch.tensor(m, dtype=torch.float32, device="cuda") for m in mats]
+    tx = torch.tensor(X, dtype=torch.float32, device="cuda")
+    ty = torch.full_like(tx, float("nan"))
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    ops = ("T", "N", "N") if dim == 2 else ("T", "N", "T")
+    fn = getattr(kron, f"kron{dim}d_batched_ex_f32")
+    # keep the side stream busy first so that its kernels start late
+    with torch.cuda.stream(side):
+        big = torch.randn(1 << 24, device="cuda")
+        for _ in range(20):
+            big = big * 1.0001
+    fn(n, *ops, 1.25, *tm, tx, 0.0, ty, batch, None, side)
+    # allocations on the current stream right after the call, overwritten at once
+    junk = [torch.full((kron.kron_ex_workspace_size(dim, n, kron.MODE_F32) // 4,), 1e30, device="cuda")
+            for _ in range(8)]
+    torch.cuda.synchronize()
+    del junk, big
+    got = ty.double().cpu().numpy()
+    hm = [t.double().cpu().numpy() for t in tm]
+    if dim == 2:
+        want = oracle.kron2d_ex(n, ops[0], ops[1], 1.25, *hm, X.astype(np.float32).astype(np.float64), 0.0,
+                                np.zeros(X.size), batch, opX="N")
+    else:
+        want = oracle.kron3d_ex(n, *ops, 1.25, *hm, X.astype(np.float32).astype(np.float64), 0.0, np.zeros(X.size),
+                                batch)
+    err = np.linalg.norm(got - want) / np.linalg.norm(want)
+    assert np.all(np.isfinite(got)) and err <= 1e-5, err

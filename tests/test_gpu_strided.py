@@ -208,3 +208,36 @@ def test_strided_argument_checks():
         kron.kron2d_batched_strided_f32(n, "N", "N", "N", 1.0, A, n, A, n, X, n, n * n, 0.0, Y, n, n * n + 1, batch)
     with pytest.raises(ValueError):   # overlapping X and Y
         kron.kron2d_batched_strided_f32(n, "N", "N", "N", 1.0, A, n, A, n, X, n, n * n, 0.0, X, n, n * n, batch)
+
+
+@pytest.mark.parametrize("n", [3, 16])
+def test_factor_axis_roles_with_permutations(n):
+    """Which factor acts on which axis of the strided 3-D entry point: with
+    distinct permutation factors and index-coded X, the result is exactly the
+    gathered copy Y[l, m, k] = X[pc[l], pb[m], pa[k]] (l fastest): C acts on
+    the fastest index l, B on m and A on the slowest index k, i.e. the paper's
+    K(C, B, A) in TKRON3's argument roles.  Padded strides, bitwise."""
+    _need_gpu()
+    rng = np.random.default_rng(5150 + n)
+    pa, pb, pc = (rng.permutation(n) for _ in range(3))
+    batch, ld = 5, n + 3
+    ld2, ldp = ld * (n + 1), ld * (n + 1) * (n + 2)
+
+    def perm_cm(p):
+        P = np.zeros((n, n))
+        P[np.arange(n), p] = 1.0
+        return torch.tensor(P.T.reshape(-1), dtype=torch.float32, device="cuda")
+
+    xi = _index(n, 3, (ld, ld2, ldp), batch)
+    xbuf = np.zeros(int(xi.max()) + 1)
+    xbuf[xi] = np.arange(xi.size) + 1.0
+    ybuf = np.full(int(xi.max()) + 1, SENTINEL)
+    tx = torch.tensor(xbuf, dtype=torch.float32, device="cuda")
+    ty = torch.tensor(ybuf, dtype=torch.float32, device="cuda")
+    kron.kron3d_batched_strided_f32(n, "N", "N", "N", 1.0, perm_cm(pa), n, perm_cm(pb), n, perm_cm(pc), n, tx, ld,
+                                    ld2, ldp, 0.0, ty, ld, ld2, ldp, batch)
+    torch.cuda.synchronize()
+    got = ty.double().cpu().numpy()[xi].reshape(batch, n, n, n)   # [p, k, m, l]
+    Xv = (np.arange(xi.size) + 1.0).reshape(batch, n, n, n)
+    want = Xv[:, pa][:, :, pb][:, :, :, pc]
+    assert np.array_equal(got, want)
