@@ -53,8 +53,17 @@ class Oracle:
         lib.oracle_kron3d_ex_f64.restype = None
         lib.oracle_kron1d_ex_f64.argtypes = [ctypes.c_int, ch, d, p, p, i64, d, p, i64, i64]
         lib.oracle_kron1d_ex_f64.restype = None
+        ip, lp = ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int64)
+        lib.oracle_kron_nd_f64.argtypes = [ctypes.c_int, ip, ip, ctypes.c_char_p, d, ctypes.POINTER(p), ip, lp,
+                                           p, d, p, i64]
+        lib.oracle_kron_nd_f64.restype = None
+        lib.oracle_kron_nd_z64.argtypes = [ctypes.c_int, ip, ip, ctypes.c_char_p, d, d, ctypes.POINTER(p), ip, lp,
+                                           p, d, d, p, i64]
+        lib.oracle_kron_nd_z64.restype = None
         lib.oracle_num_threads.argtypes = []
         lib.oracle_num_threads.restype = ctypes.c_int
+        lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
+        lib.oracle_set_num_threads.restype = None
         self.lib = lib
         self.path = path
 
@@ -138,9 +147,47 @@ class Oracle:
                                       _ptr(C), _ptr(X), beta, _ptr(Y), batch)
         return Y
 
+    def kron_nd(self, m, n, ops, alpha, factors, X, beta, Y, batch, ldf=None, ldfp=None):
+        """vec(Y_p) <- alpha (op(F_0) kron .. kron op(F_{d-1})) vec(X_p) + beta vec(Y_p)
+        for d-dimensional operands (last index fastest), op(F_k) m[k] x n[k]
+        ('N', 'T' or 'C'), F_k of operand p at factors[k][p * ldfp[k]:]
+        (column-major, leading dimension ldf[k]); real FP64, or complex128
+        when any input is complex.  Returns the new Y (a copy)."""
+        d = len(m)
+        if not (1 <= d <= 8 and len(n) == d and len(ops) == d and len(factors) == d):
+            raise ValueError("d must be in 1..8 with one size, op and factor per dimension")
+        cplx = any(np.iscomplexobj(a) for a in list(factors) + [X, Y, alpha, beta])
+        dt = np.complex128 if cplx else np.float64
+        ldf = [int(m[k] if ops[k] in "Nn" else n[k]) for k in range(d)] if ldf is None else [int(v) for v in ldf]
+        ldfp = [0] * d if ldfp is None else [int(v) for v in ldfp]
+        fs = [np.ascontiguousarray(np.asarray(f).reshape(-1), dtype=dt) for f in factors]
+        for k in range(d):
+            rows, cols = (m[k], n[k]) if ops[k] in "Nn" else (n[k], m[k])
+            need = (rows + ldf[k] * (cols - 1)) + (batch - 1) * ldfp[k] if batch > 0 else 0
+            if ldf[k] < rows or fs[k].size < need:
+                raise ValueError(f"factor {k}: leading dimension or size too small")
+        nx, ny = int(np.prod(n)), int(np.prod(m))
+        X = _prep(X, dt, batch * nx)
+        Y = np.array(_prep(Y, dt, batch * ny), copy=True)
+        ci = (ctypes.c_int * d)
+        fp = (ctypes.c_void_p * d)(*[f.ctypes.data for f in fs])
+        args = (d, ci(*m), ci(*n), "".join(ops).encode(), )
+        if cplx:
+            a, b = complex(alpha), complex(beta)
+            self.lib.oracle_kron_nd_z64(*args, a.real, a.imag, fp, ci(*ldf), (ctypes.c_int64 * d)(*ldfp),
+                                        _ptr(X), b.real, b.imag, _ptr(Y), batch)
+        else:
+            self.lib.oracle_kron_nd_f64(*args, float(alpha), fp, ci(*ldf), (ctypes.c_int64 * d)(*ldfp), _ptr(X),
+                                        float(beta), _ptr(Y), batch)
+        return Y
+
     def num_threads(self):
         """OpenMP threads the oracle uses."""
         return int(self.lib.oracle_num_threads())
+
+    def set_num_threads(self, n):
+        """OpenMP threads of later calls (timing on a stated core count)."""
+        self.lib.oracle_set_num_threads(int(n))
 
 
 def _ptr(a):
@@ -206,3 +253,7 @@ def kron1d_ex(*args, **kw):
 
 def kron3d_ex(*args, **kw):
     return default().kron3d_ex(*args, **kw)
+
+
+def kron_nd(*args, **kw):
+    return default().kron_nd(*args, **kw)

@@ -336,3 +336,120 @@ ORACLE_API int oracle_num_threads(void) {
 #endif
   return t;
 }
+
+/* Set the number of OpenMP threads of later calls (for timing on a given
+   core count); n < 1 is ignored. */
+ORACLE_API void oracle_set_num_threads(int n) {
+#ifdef _OPENMP
+  extern void omp_set_num_threads(int);
+  if (n >= 1) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
+/* ---- d-dimensional arrays, rectangular, complex, per-operand factors -------
+ *
+ * Section 2.1 generalises the action to n-D arrays for any n >= 1 (the
+ * summation gains one index and one factor per dimension), Section 2.2
+ * allows op(M) in {M, M^T, M^*} with op(M) of size m x n, complex entries,
+ * and alpha / beta, and Section 6 names the case where the factors change
+ * along the batch.  Written out for operand p:
+ *
+ *   Y_p(i_0, .., i_{d-1}) <- alpha * sum_{a_0, .., a_{d-1}}
+ *        op(F_0)(i_0, a_0) * .. * op(F_{d-1})(i_{d-1}, a_{d-1}) * X_p(a_0, .., a_{d-1})
+ *      + beta * Y_p(i_0, .., i_{d-1})
+ *
+ * with the library's convention that the last index is the fastest in
+ * memory (element (a_0, .., a_{d-1}) of X_p at sum_k a_k * prod_{j>k} n_j, and
+ * vec(Y_p) = (op(F_0) (x) .. (x) op(F_{d-1})) vec(X_p)).  X_p has extents
+ * n_0 .. n_{d-1} and starts at p * prod(n); Y_p has extents m_0 .. m_{d-1}
+ * and starts at p * prod(m).  F_k of operand p starts at F[k] + p * ldfp[k]
+ * (ldfp[k] = 0: one matrix shared by the batch) and is stored column-major
+ * with leading dimension ldf[k]; the stored matrix is m_k x n_k for 'N' and
+ * n_k x m_k for 'T' / 'C' ('C' also conjugates).  beta == 0 does not read Y.
+ *
+ * Computed as d mode products, fastest index first: contracting index k
+ * replaces extent n_k by m_k.  Complex numbers are (re, im) pairs of doubles.
+ */
+#include <complex.h>
+
+#define ND_MAX_DIM 8
+
+static int64_t nd_prod(const int* e, int d) {
+  int64_t s = 1;
+  for (int k = 0; k < d; ++k) s *= e[k];
+  return s;
+}
+
+/* op(F)(i, a) for the stored matrix M with leading dimension ld */
+#define ND_OP_ENTRY(T, CONJ, M, ld, op, i, a)                                        \
+  ((op) == 'N' || (op) == 'n' ? (M)[(i) + (int64_t)(ld) * (a)]                       \
+   : ((op) == 'T' || (op) == 't') ? (M)[(a) + (int64_t)(ld) * (i)]                   \
+   : CONJ((M)[(a) + (int64_t)(ld) * (i)]))
+
+#define DEFINE_KRON_ND(NAME, T, CONJ)                                                \
+  static void NAME(int d, const int* m, const int* n, const char* ops, T alpha,      \
+                   const T* const* F, const int* ldf, const int64_t* ldfp,           \
+                   const T* X, T beta, T* Y, int64_t batch) {                        \
+    const int64_t nx = nd_prod(n, d), ny = nd_prod(m, d);                            \
+    int64_t big = 1; /* largest intermediate: max over passes of its extents */      \
+    for (int k = d; k >= 0; --k) {                                                   \
+      int e[ND_MAX_DIM];                                                             \
+      for (int j = 0; j < d; ++j) e[j] = j < k ? n[j] : m[j];                        \
+      const int64_t s = nd_prod(e, d);                                               \
+      if (s > big) big = s;                                                          \
+    }                                                                                \
+    _Pragma("omp parallel for schedule(dynamic)")                                    \
+    for (int64_t p = 0; p < batch; ++p) {                                            \
+      T* cur = (T*)malloc(sizeof(T) * big);                                          \
+      T* nxt = (T*)malloc(sizeof(T) * big);                                          \
+      int e[ND_MAX_DIM];                                                             \
+      for (int j = 0; j < d; ++j) e[j] = n[j];                                       \
+      for (int64_t q = 0; q < nx; ++q) cur[q] = X[p * nx + q];                       \
+      for (int k = d - 1; k >= 0; --k) {                                             \
+        /* cur has extents e; contract index k: pre x n_k x post -> pre x m_k x post */ \
+        int64_t pre = 1, post = 1;                                                   \
+        for (int j = 0; j < k; ++j) pre *= e[j];                                     \
+        for (int j = k + 1; j < d; ++j) post *= e[j];                                \
+        const T* M = F[k] + p * ldfp[k];                                             \
+        for (int64_t u = 0; u < pre; ++u)                                            \
+          for (int i = 0; i < m[k]; ++i)                                             \
+            for (int64_t v = 0; v < post; ++v) {                                     \
+              T s = 0;                                                               \
+              for (int a = 0; a < n[k]; ++a)                                         \
+                s += ND_OP_ENTRY(T, CONJ, M, ldf[k], ops[k], i, a) *                 \
+                     cur[(u * n[k] + a) * post + v];                                 \
+              nxt[(u * m[k] + i) * post + v] = s;                                    \
+            }                                                                        \
+        e[k] = m[k];                                                                 \
+        T* t = cur; cur = nxt; nxt = t;                                              \
+      }                                                                              \
+      for (int64_t q = 0; q < ny; ++q) {                                             \
+        T v = alpha * cur[q];                                                        \
+        Y[p * ny + q] = beta == (T)0 ? v : v + beta * Y[p * ny + q];                 \
+      }                                                                              \
+      free(cur);                                                                     \
+      free(nxt);                                                                     \
+    }                                                                                \
+  }
+
+#define ND_NO_CONJ(x) (x)
+DEFINE_KRON_ND(kron_nd_real, double, ND_NO_CONJ)
+DEFINE_KRON_ND(kron_nd_cplx, double _Complex, conj)
+
+/* Real FP64. */
+ORACLE_API void oracle_kron_nd_f64(int d, const int* m, const int* n, const char* ops, double alpha,
+                                   const double* const* F, const int* ldf, const int64_t* ldfp, const double* X,
+                                   double beta, double* Y, int64_t batch) {
+  kron_nd_real(d, m, n, ops, alpha, F, ldf, ldfp, X, beta, Y, batch);
+}
+
+/* Complex FP64: every array holds (re, im) pairs of doubles. */
+ORACLE_API void oracle_kron_nd_z64(int d, const int* m, const int* n, const char* ops, double alpha_re,
+                                   double alpha_im, const double* const* F, const int* ldf, const int64_t* ldfp,
+                                   const double* X, double beta_re, double beta_im, double* Y, int64_t batch) {
+  const double _Complex alpha = alpha_re + alpha_im * I, beta = beta_re + beta_im * I;
+  kron_nd_cplx(d, m, n, ops, alpha, (const double _Complex* const*)F, ldf, ldfp, (const double _Complex*)X, beta,
+               (double _Complex*)Y, batch);
+}

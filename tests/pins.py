@@ -432,3 +432,137 @@ ALL_PINS = [
     pin_rank_one, pin_triple_sum, pin_linearity, pin_batch_independence,
     pin_gradients, pin_float_accuracy, pin_extended_interface, pin_tkron1,
 ]
+
+
+# ---- the general action: d dimensions, rectangular, complex, per operand ----
+
+def _read_nd_golden():
+    vals = {}
+    with open(os.path.join(GOLDEN, "worked_nd.txt")) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            key, *rest = line.split()
+            if key.endswith("_ops"):
+                vals[key] = rest[0]
+            elif key.endswith(("_m", "_n")):
+                vals[key] = [int(v) for v in rest]
+            else:
+                vals[key] = np.array([complex(*map(float, v.split(","))) if "," in v else float(v) for v in rest])
+    return vals
+
+
+def pin_nd_worked_examples(orc):
+    g = _read_nd_golden()
+    for tag in ("c", "r"):
+        m, n, ops = g[tag + "_m"], g[tag + "_n"], g[tag + "_ops"]
+        fs = [g[f"{tag}_F{k}"] for k in range(len(m))]
+        ldf = [m[k] if ops[k] == "N" else n[k] for k in range(len(m))]
+        Y = orc.kron_nd(m, n, ops, 1.0, fs, g[tag + "_X"], 0.0, np.zeros(int(np.prod(m))), 1, ldf=ldf)
+        assert np.allclose(Y, g[tag + "_Y"], rtol=0, atol=1e-14), (tag, Y)
+
+
+def _opm(S, op):
+    """op(S) of a math matrix: 'N' S, 'T' S^T, 'C' S^* (conjugate transpose)."""
+    return S if op == "N" else (S.T if op == "T" else S.conj().T)
+
+
+def _nd_random_case(rng, d, cplx, varying, batch):
+    m = [int(v) for v in rng.integers(1, 5, d)]
+    n = [int(v) for v in rng.integers(1, 5, d)]
+    ops = "".join(rng.choice(list("NTC" if cplx else "NT"), d))
+    ldf, ldfp, fs, mats = [], [], [], []
+    for k in range(d):
+        rows, cols = (m[k], n[k]) if ops[k] == "N" else (n[k], m[k])
+        ld = rows + int(rng.integers(0, 3))
+        stride = ld * cols + int(rng.integers(0, 4)) if varying else 0
+        count = batch if varying else 1
+        size = (count - 1) * stride + ld * cols
+        flat = rng.uniform(-1, 1, size) + (1j * rng.uniform(-1, 1, size) if cplx else 0)
+        per = []
+        for p in range(count):
+            blk = flat[p * stride:p * stride + ld * cols].reshape(cols, ld).T[:rows]   # column-major, ld rows
+            per.append(_opm(blk, ops[k]))
+        ldf.append(ld)
+        ldfp.append(stride)
+        fs.append(flat)
+        mats.append(per)
+    X = rng.standard_normal(batch * int(np.prod(n))) + (1j * rng.standard_normal(batch * int(np.prod(n))) if cplx else 0)
+    return m, n, ops, fs, ldf, ldfp, mats, X
+
+
+def pin_nd_brute_force(orc, seed=16):
+    """Explicit Kronecker matrices (numpy.kron of op(F_k), per operand when the
+    factors vary) on memory-order vectors, with alpha, beta and padded
+    leading dimensions: d = 1..4, rectangular, real and complex."""
+    rng = np.random.default_rng(seed)
+    for trial in range(24):
+        d = 1 + trial % 4
+        cplx = bool(trial % 2)
+        varying = trial % 3 == 0
+        batch = 3
+        m, n, ops, fs, ldf, ldfp, mats, X = _nd_random_case(rng, d, cplx, varying, batch)
+        ny = int(np.prod(m))
+        alpha = 1.5 - 0.5j if cplx else -0.75
+        beta = (0.25 + 1j if cplx else 2.0) if trial % 4 == 1 else 0.0
+        Y0 = rng.standard_normal(batch * ny) + (1j * rng.standard_normal(batch * ny) if cplx else 0)
+        got = orc.kron_nd(m, n, ops, alpha, fs, X, beta, Y0, batch, ldf=ldf, ldfp=ldfp)
+        nx = int(np.prod(n))
+        for p in range(batch):
+            K = np.ones((1, 1))
+            for k in range(d):
+                K = np.kron(K, mats[k][p if varying else 0])
+            want = alpha * (K @ X[p * nx:(p + 1) * nx]) + beta * Y0[p * ny:(p + 1) * ny]
+            assert np.allclose(got[p * ny:(p + 1) * ny], want, rtol=1e-13, atol=1e-13), (trial, p)
+
+
+def pin_nd_adjoint(orc, seed=17):
+    """<K(op(F)) X, Z> = <X, K(op'(F)) Z> with op' the conjugate transpose of op
+    ('N' <-> 'C' on the same stored matrices; complex inner product)."""
+    rng = np.random.default_rng(seed)
+    flip = {"N": "C", "C": "N"}
+    for d in (1, 2, 3):
+        m = [int(v) for v in rng.integers(1, 5, d)]
+        n = [int(v) for v in rng.integers(1, 5, d)]
+        ops = "".join(rng.choice(["N", "C"], d))
+        fs, ldf = [], []
+        for k in range(d):
+            rows, cols = (m[k], n[k]) if ops[k] == "N" else (n[k], m[k])
+            fs.append(rng.standard_normal(rows * cols) + 1j * rng.standard_normal(rows * cols))
+            ldf.append(rows)
+        X = rng.standard_normal(int(np.prod(n))) + 1j * rng.standard_normal(int(np.prod(n)))
+        Z = rng.standard_normal(int(np.prod(m))) + 1j * rng.standard_normal(int(np.prod(m)))
+        KX = orc.kron_nd(m, n, ops, 1.0, fs, X, 0.0, np.zeros(Z.size, complex), 1, ldf=ldf)
+        KhZ = orc.kron_nd(n, m, "".join(flip[o] for o in ops), 1.0, fs, Z, 0.0, np.zeros(X.size, complex), 1,
+                          ldf=ldf)
+        lhs, rhs = np.vdot(Z, KX), np.vdot(KhZ, X)
+        assert abs(lhs - rhs) <= 1e-12 * (1 + abs(lhs)), (d, lhs, rhs)
+
+
+def pin_nd_special_cases(orc, seed=18):
+    """d = 1 is a batched matrix-vector product (numpy.matmul); identity
+    factors copy; with square real shared factors, d = 2 and 3 equal the
+    pinned 2-D / 3-D actions; a NaN-filled Y with beta = 0 is not read."""
+    rng = np.random.default_rng(seed)
+    A = rng.uniform(-1, 1, (5, 3))
+    X = rng.standard_normal(4 * 3)
+    got = orc.kron_nd([5], [3], "N", 1.0, [cm(A)], X, 0.0, np.full(4 * 5, np.nan), 4)
+    assert np.allclose(got.reshape(4, 5), np.matmul(A, X.reshape(4, 3).T).T, rtol=1e-14, atol=1e-14)
+    dims = [2, 3, 4]
+    I = [cm(np.eye(k)) for k in dims]
+    Xc = rng.standard_normal(2 * 24) + 1j * rng.standard_normal(2 * 24)
+    assert np.array_equal(orc.kron_nd(dims, dims, "NTC", 1.0, I, Xc, 0.0, np.zeros(48, complex), 2), Xc)
+    n = 4
+    mats = rand_mats(rng, n, 3)
+    X3 = rng.standard_normal(3 * n ** 3)
+    want = orc.kron3d_ex(n, "T", "N", "T", 1.25, *mats, X3, 0.0, np.zeros(X3.size), 3)
+    got = orc.kron_nd([n] * 3, [n] * 3, "TNT", 1.25, mats, X3, 0.0, np.zeros(X3.size), 3)
+    assert rel(got, want) <= 1e-14
+    X2 = rng.standard_normal(3 * n * n)
+    want = orc.kron2d_ex(n, "N", "T", -2.0, mats[0], mats[1], X2, 0.5, X2[::-1].copy(), 3)
+    got = orc.kron_nd([n] * 2, [n] * 2, "NT", -2.0, mats[:2], X2, 0.5, X2[::-1].copy(), 3)
+    assert rel(got, want) <= 1e-14
+
+
+ALL_PINS += [pin_nd_worked_examples, pin_nd_brute_force, pin_nd_adjoint, pin_nd_special_cases]

@@ -48,6 +48,17 @@ MUTATIONS = {
     "tkron1_transpose_ignored": ("  op_matrix(n, opA, A, Ao);\n  for (int64_t p = 0; p < batch; ++p) {\n    const double* x = X + p * ldxp;",
                                  "  op_matrix(n, 'N', A, Ao);\n  for (int64_t p = 0; p < batch; ++p) {\n    const double* x = X + p * ldxp;"),
     "tkron1_output_stride": ("    double* y = Y + p * ldyp;", "    double* y = Y + p * ldxp;"),
+    "nd_op_n_transposed": ("((op) == 'N' || (op) == 'n' ? (M)[(i) + (int64_t)(ld) * (a)]",
+                           "((op) == 'N' || (op) == 'n' ? (M)[(a) + (int64_t)(ld) * (i)]"),
+    "nd_conj_dropped": ("DEFINE_KRON_ND(kron_nd_cplx, double _Complex, conj)",
+                        "DEFINE_KRON_ND(kron_nd_cplx, double _Complex, ND_NO_CONJ)"),
+    "nd_per_operand_factor_ignored": ("const T* M = F[k] + p * ldfp[k];", "const T* M = F[k];"),
+    "nd_dropped_term": ("for (int a = 0; a < n[k]; ++a)", "for (int a = 1; a < n[k]; ++a)"),
+    "nd_alpha_dropped": ("T v = alpha * cur[q];", "T v = cur[q];"),
+    "nd_beta_zero_reads_y": ("Y[p * ny + q] = beta == (T)0 ? v : v + beta * Y[p * ny + q];",
+                             "Y[p * ny + q] = v + beta * Y[p * ny + q];"),
+    "nd_wrong_post_index": ("cur[(u * n[k] + a) * post + v];", "cur[(u * n[k] + a) * post + (post - 1 - v)];"),
+    "nd_output_row_index": ("nxt[(u * m[k] + i) * post + v] = s;", "nxt[(u * m[k] + (m[k] - 1 - i)) * post + v] = s;"),
     "f32_accumulates_in_double": ("DEFINE_KRON2D(oracle_kron2d_f32, float)", "DEFINE_KRON2D(oracle_kron2d_f32_unused, float)\nORACLE_API void oracle_kron2d_f32(int n, const float* A, const float* B, const float* X, float* Y, int64_t batch) { (void)A; (void)B; for (int64_t i = 0; i < batch * n * n; ++i) Y[i] = X[i]; }"),
 }
 
