@@ -27,8 +27,10 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, vendor figure
 PAPER_K20C = {("f32", 3, 16): 268, ("f32", 2, 16): 285, ("f32", 3, 10): 126, ("f32", 2, 10): 143,
               ("f64", 3, 16): 169, ("f64", 2, 16): 152, ("f64", 3, 10): 103, ("f64", 2, 10): 108}
-KERNEL_SOURCES = ["paper_1304_7054_amd/csrc/kron_tile.hpp", "paper_1304_7054_amd/csrc/kron_kernels.hpp",
-                  "paper_1304_7054_amd/csrc/kron_launch.hpp", "paper_1304_7054_amd/csrc/kron_abi.hip"]
+# every library source and header: the counter-derived traffic of the
+# headline kernel is reported only for the code and flags it was taken on
+KERNEL_SOURCE_DIRS = ["paper_1304_7054_amd/csrc"]
+KERNEL_HEADERS = ["include/kron.h"]
 
 
 def parse():
@@ -39,6 +41,8 @@ def parse():
     p.add_argument("--device-warm", type=float, default=0.5,
                    help="seconds of untimed launches before each measurement's warm-up steps (steady clocks)")
     p.add_argument("--only-headline", action="store_true", help="skip the other modes")
+    p.add_argument("--only", default="", help="comma-separated names of the measurements to run after the "
+                   "headline (see measurement_plan), e.g. grouped,grouped-backward")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--summarize-profiles", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
                    help="read rocprofv3 outputs of this script (kernel trace, FETCH_SIZE, WRITE_SIZE runs "
@@ -52,11 +56,24 @@ def parse():
     return p.parse_args()
 
 
+def kernel_sources():
+    files = []
+    for d in KERNEL_SOURCE_DIRS:
+        files += sorted(os.path.join(d, f) for f in os.listdir(os.path.join(ROOT, d))
+                        if f.endswith((".hip", ".hpp", ".h")))
+    return files + KERNEL_HEADERS
+
+
 def kernel_hash():
+    """Hash of every library source and the device compile flags (include
+    paths left out: they name the checkout's location)."""
+    from paper_1304_7054_amd import build as kbuild
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in kernel_sources():
+        h.update(f.encode())
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
+    h.update(" ".join(a for a in kbuild.COMMON if not a.startswith("-I")).encode())
     return h.hexdigest()[:16]
 
 
@@ -157,12 +174,116 @@ def measure(torch, mode, dim, n, batch, steps, warmup, seed):
     return out
 
 
+def measure_copy(torch, steps, warmup):
+    """A plain 1 GiB device-to-device copy (torch copy_, 1 GiB read + 1 GiB
+    written) timed like the kernels: the achievable-bandwidth reference."""
+    src = torch.ones(1 << 28, device="cuda")
+    dst = torch.empty_like(src)
+    wall, kmean, kmin = time_launches(torch, lambda stream=None: dst.copy_(src), (), steps, warmup)
+    del src, dst
+    torch.cuda.empty_cache()
+    gbs = 2 * (1 << 30) / (kmean * 1e-3) / 1e9
+    return {"bytes": 2 * (1 << 30), "ms": round(kmean, 4), "gbs": round(gbs, 1),
+            "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+
+def batch_errors(mode, n, mats_exact, X_dev, Y_dev, batch, chunk=4096):
+    """Normwise relative error over the whole batch (and the largest
+    per-array one) of a 3-D result against the FP64 oracle applied to
+    `mats_exact` and the device operands, computed on the host in chunks.
+    bf16 storage: X_dev holds the bf16 operands; the oracle sees their
+    exact values."""
+    import oracle
+    e = n ** 3
+    num = den = 0.0
+    worst = 0.0
+    for s0 in range(0, batch, chunk):
+        b = min(chunk, batch - s0)
+        x = X_dev[s0 * e:(s0 + b) * e].double().cpu().numpy()
+        y = Y_dev[s0 * e:(s0 + b) * e].double().cpu().numpy()
+        want = oracle.kron3d(n, *mats_exact, x, b, "f64")
+        d = (y - want).reshape(b, e)
+        w = want.reshape(b, e)
+        dn = np.einsum("ij,ij->i", d, d)
+        wn = np.einsum("ij,ij->i", w, w)
+        num += float(dn.sum())
+        den += float(wn.sum())
+        worst = max(worst, float(np.sqrt((dn / np.maximum(wn, 1e-300)).max())))
+    return float(np.sqrt(num / den)), worst
+
+
+def measure_precision(torch, steps, warmup):
+    """The precision workload: 3-D n = 16, 65,536 arrays, every entry of A, B,
+    C and X log-uniform in magnitude on [1e-3, 1e3] with a random sign
+    (factors drawn on the host, operands with a seeded device generator).
+    Plain FP32, bf16x3 (FP32 I/O) and bf16 storage are timed on the same
+    values, and each result is compared with the FP64 oracle over the whole
+    batch.  bf16 storage rounds its inputs to bf16 (nearest even): its error
+    is given against the oracle on the original FP32 values (the figure of
+    merit) and on the rounded inputs (arithmetic and output rounding only)."""
+    import workloads
+    n, batch = 16, workloads.BATCH_3D[16]
+    rng = workloads.rng_for(3)
+    mats32 = [workloads.log_uniform(rng, n * n, np.float32) for _ in range(3)]
+    gen = torch.Generator(device="cuda").manual_seed(workloads.SEED_BASE + 3)
+    X = workloads.log_uniform_device_(torch.empty(batch * n ** 3, device="cuda"), gen)
+    Y = torch.empty_like(X)
+    tm = [torch.from_numpy(m).to("cuda") for m in mats32]
+    exact32 = [m.astype(np.float64) for m in mats32]
+    out = []
+    for mode in ("f32", "bf16x3", "bf16"):
+        if mode == "bf16":
+            tmb = [t.to(torch.bfloat16) for t in tm]
+            Xb = X.to(torch.bfloat16)
+            Yb = torch.empty_like(Xb)
+            args = (n, *tmb, Xb, Yb, batch)
+        else:
+            args = (n, *tm, X, Y, batch)
+        wall, kmean, kmin = time_launches(torch, fn_for(mode, 3), args, steps, warmup)
+        bytes_per = (2 if mode == "bf16" else 4) * n ** 3 * 2
+        gbs = bytes_per * batch / (kmean * 1e-3) / 1e9
+        rec = {"mode": mode, "dim": 3, "n": n, "batch": batch,
+               "data": "log-uniform magnitudes in [1e-3, 1e3], random signs (A, B, C and X)",
+               "ms": round(kmean, 4), "ms_min": round(kmin, 4), "wall_ms_per_step": round(wall, 4),
+               "gflops": round(batch * flops_per_op(3, n) / (kmean * 1e-3) / 1e9, 1), "gbs": round(gbs, 1),
+               "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "alg_bytes": bytes_per * batch}
+        if mode == "bf16":
+            # (i) against the original FP32 values; (ii) against the rounded inputs
+            norm, worst = batch_errors(mode, n, exact32, X, Yb, batch)
+            rounded = [t.double().cpu().numpy() for t in tmb]
+            norm2, worst2 = batch_errors(mode, n, rounded, Xb, Yb, batch)
+            rec.update({"rel_err_vs_fp32_inputs": norm, "max_array_rel_err_vs_fp32_inputs": worst,
+                        "rel_err_vs_bf16_inputs": norm2, "max_array_rel_err_vs_bf16_inputs": worst2})
+            del tmb, Xb, Yb
+        else:
+            norm, worst = batch_errors(mode, n, exact32, X, Y, batch)
+            rec.update({"rel_err": norm, "max_array_rel_err": worst})
+        rec["error_scope"] = "whole batch, normwise (Frobenius) against the FP64 oracle"
+        out.append(rec)
+        print(f"# measured precision workload {mode}: {rec['gflops']} GFLOP/s", file=sys.stderr, flush=True)
+    del X, Y, tm
+    torch.cuda.empty_cache()
+    return out
+
+
+_MIXED = None
+
+
+def mixed_workload():
+    """The 500,000-operand mixed workload (drawn once per run)."""
+    global _MIXED
+    if _MIXED is None:
+        import workloads
+        _MIXED = workloads.workload4()
+    return _MIXED
+
+
 def measure_grouped(torch, steps, warmup):
     """The 500,000-operand mixed workload (n in 2..16, 70/30 2-D/3-D, one
     group per (dim, n)) in one persistent launch, replayed from a HIP graph."""
     import paper_1304_7054_amd as kron
     import workloads
-    probs = workloads.workload4()
+    probs = mixed_workload()
     groups, flops, alg = [], 0, 0
     for p in probs:
         g = {"dim": p.dim, "n": p.n, "count": p.batch, "X": torch.from_numpy(p.X).to("cuda"),
@@ -203,6 +324,128 @@ def measure_grouped(torch, steps, warmup):
             "gflops": round(flops / (kmean * 1e-3) / 1e9, 1), "gbs": round(alg / (kmean * 1e-3) / 1e9, 1),
             "hbm_frac": round(alg / (kmean * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "alg_bytes": alg,
             "sampled_max_rel_err": worst}
+
+
+def measure_grouped_backward(torch, steps, warmup):
+    """Backward over the 500,000-operand mixed workload: every group's dX and
+    its batch-reduced dA, dB (, dC) from upstream gradients dY ~ N(0, 1), in
+    one kron_grouped_backward call (reads X and dY, writes dX: three streams
+    of the workload's operand bytes; the factor gradients are negligible)."""
+    import paper_1304_7054_amd as kron
+    import workloads
+    probs = mixed_workload()
+    groups, alg, flops = [], 0, 0
+    for p in probs:
+        g = {"dim": p.dim, "n": p.n, "count": p.batch, "X": torch.from_numpy(p.X).to("cuda"),
+             "dY": torch.from_numpy(p.dY).to("cuda")}
+        g["dX"] = torch.empty_like(g["X"])
+        for k, m in zip("ABC", (p.A, p.B, p.C)):
+            if m is not None:
+                g[k] = torch.from_numpy(m).to("cuda")
+                g["d" + k] = torch.empty(p.n * p.n, device="cuda")
+        groups.append(g)
+        alg += 3 * 4 * p.X.size
+        flops += p.flops()
+    ws = torch.empty(kron.kron_grouped_backward_workspace_size(groups), dtype=torch.uint8, device="cuda")
+    wall, kmean, kmin = time_launches(torch, lambda stream=None: kron.kron_grouped_backward(groups, ws, stream), (),
+                                      steps, warmup)
+    torch.cuda.synchronize()
+    # sampled parity: the factor gradients of the two largest-n groups against the FP64 oracle
+    import oracle
+    worst = 0.0
+    for p, g in [(p, g) for p, g in zip(probs, groups) if p.n == 16]:
+        mats = [m.astype(np.float64) for m in (p.A, p.B, p.C) if m is not None]
+        grad = oracle.kron2d_grad if p.dim == 2 else oracle.kron3d_grad
+        want = grad(p.n, *mats, p.X.astype(np.float64), p.dY.astype(np.float64), p.batch)
+        for k, w in zip("ABC", want[1:]):
+            got = g["d" + k].double().cpu().numpy()
+            worst = max(worst, float(np.linalg.norm(got - w) / np.linalg.norm(w)))
+    del groups, ws
+    torch.cuda.empty_cache()
+    return {"mode": "f32 grouped backward (500,000 mixed operands: dX, dA, dB, dC per group)",
+            "operands": workloads.MIXED_COUNT, "groups": len(probs), "ms": round(kmean, 4), "ms_min": round(kmin, 4),
+            "wall_ms_per_step": round(wall, 4), "gbs": round(alg / (kmean * 1e-3) / 1e9, 1),
+            "hbm_frac": round(alg / (kmean * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "alg_bytes": alg,
+            "forward_gflop": round(flops / 1e9, 3), "factor_grad_rel_err_n16": worst}
+
+
+def _nd_workload(torch, case):
+    """The general-action workloads (1 GiB of operands each), drawn on the
+    device from a seeded generator: (tag, m, n, ops, factors, ldfp, X, batch,
+    flops per operand, passes)."""
+    import workloads
+    g = torch.Generator(device="cuda").manual_seed(workloads.SEED_BASE + 11)
+    if case == "f32 4-D n=16":
+        tag, dims, batch, varying = "f32", [16] * 4, 4096, False
+    elif case == "c32 3-D n=16":
+        tag, dims, batch, varying = "c32", [16] * 3, 32768, False
+    elif case == "f32 2-D n=32":
+        tag, dims, batch, varying = "f32", [32] * 2, 262144, False
+    elif case == "f32 3-D varying n=16":
+        tag, dims, batch, varying = "f32", [16] * 3, 65536, True
+    else:
+        raise KeyError(case)
+    dt = {"f32": torch.float32, "c32": torch.complex64}[tag]
+    d, n = len(dims), dims[0]
+    count = batch if varying else 1
+    fac = [(torch.rand(count * n * n, generator=g, device="cuda", dtype=torch.float64) * 2 - 1).to(dt)
+           for _ in range(d)]
+    if tag == "c32":
+        fac = [f + 1j * (torch.rand(f.numel(), generator=g, device="cuda") * 2 - 1) for f in fac]
+    X = torch.randn(batch * n ** d, generator=g, device="cuda", dtype=dt)
+    ops = "NTNC"[:d] if tag == "c32" else "NTNT"[:d]
+    # paper's flop model per real contraction (2 n^(d+1) per mode), x4 for complex arithmetic
+    flops = d * 2 * n ** (d + 1) * (4 if tag == "c32" else 1)
+    return tag, dims, dims, ops, fac, [n * n if varying else 0] * d, X, batch, flops, d
+
+
+def measure_nd(torch, case, steps=10, warmup=2, check_only=False):
+    """One general-action workload through kron_nd_batched_*: timed like the
+    other modes, sampled operands against the oracle."""
+    import paper_1304_7054_amd as kron
+    import oracle
+    tag, m, n, ops, fac, ldfp, X, batch, flops, passes = _nd_workload(torch, case)
+    Y = torch.empty(batch * int(np.prod(m)), device="cuda", dtype=X.dtype)
+    code = {"f32": kron.MODE_F32, "c32": kron.KRON_TYPE_C32}[tag]
+    ws = torch.empty(max(1, kron.kron_nd_workspace_size(m, n, batch, code)), dtype=torch.uint8, device="cuda")
+    fn = getattr(kron, f"kron_nd_batched_{tag}")
+    call = lambda stream=None: fn(m, n, ops, 1.0, fac, X, 0.0, Y, batch, ldfp=ldfp, ws=ws, stream=stream)
+    if check_only:
+        call()
+        kmean = kmin = wall = float("nan")
+    else:
+        wall, kmean, kmin = time_launches(torch, call, (), steps, warmup)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(11)
+    nx, ny = int(np.prod(n)), int(np.prod(m))
+    num = den = 0.0
+    for q in np.unique(np.concatenate([[0, batch - 1], rng.integers(0, batch, 4)])):
+        q = int(q)
+        hx = X[q * nx:(q + 1) * nx].cpu().numpy()
+        hf = [(f[q * s:q * s + nn * nn] if s else f).cpu().numpy() for f, s, nn in zip(fac, ldfp, n)]
+        want = oracle.kron_nd(m, n, ops, 1.0, hf, hx, 0.0, np.zeros(ny), 1)
+        got = Y[q * ny:(q + 1) * ny].cpu().numpy()
+        num += float(np.sum(np.abs(got - want) ** 2))
+        den += float(np.sum(np.abs(want) ** 2))
+    finite = bool(torch.isfinite(torch.view_as_real(Y) if Y.is_complex() else Y).all())
+    esz = X.element_size()
+    alg = (nx + ny) * batch * esz + (sum(int(f.numel()) for f in fac) * esz if any(ldfp) else 0)
+    out = {"mode": f"general action: {case}", "tag": tag, "batch": batch, "passes": passes,
+           "sampled_rel_err": float(np.sqrt(num / den)) if finite else float("inf")}
+    if not check_only:
+        gbs = alg / (kmean * 1e-3) / 1e9
+        out.update({"ms": round(kmean, 4), "ms_min": round(kmin, 4), "wall_ms_per_step": round(wall, 4),
+                    "gflops": round(batch * flops / (kmean * 1e-3) / 1e9, 1), "gbs": round(gbs, 1),
+                    "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "alg_bytes": alg,
+                    "pass_bytes": passes * (nx + ny) * batch * esz,
+                    "pass_traffic_frac": round(passes * (nx + ny) * batch * esz / (kmean * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)})
+    del fac, X, Y, ws
+    torch.cuda.empty_cache()
+    return out
+
+
+ND_CASES = {c: (lambda torch, check_only=False, c=c: measure_nd(torch, c, check_only=check_only))
+            for c in ("f32 4-D n=16", "c32 3-D n=16", "f32 2-D n=32", "f32 3-D varying n=16")}
 
 
 def measure_ex(torch, steps, warmup, beta=0.0):
@@ -417,11 +660,39 @@ def measure_backward(torch, steps, warmup):
             "alg_bytes": alg}
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def _oracle_rate(orc, call, flops, target_s, max_passes=200):
+    """Whole passes of `call` until about target_s seconds have run (after
+    one warm pass); returns (GFLOP/s, passes, seconds)."""
+    call()
+    passes, t = 0, time.perf_counter()
+    while True:
+        call()
+        passes += 1
+        dt = time.perf_counter() - t
+        if dt >= target_s or passes >= max_passes:
+            return passes * flops / dt / 1e9, passes, dt
+
+
 def cpu_baseline(n=16, target_s=10.0):
-    """The FP32 CPU oracle on a bounded sample of the headline workload."""
+    """The CPU oracle on a bounded sample of the headline workload: FP32 (the
+    reported value) and FP64 on every host core, and the small 2-D n = 4
+    workload (4096 operands) on one core."""
     import oracle
     import workloads
     orc = oracle.default()
+    cores = orc.num_threads()
     rng = workloads.rng_for(2)
     A, B, C = (workloads.uniform(rng, n * n, np.float32) for _ in range(3))
     probe = 256
@@ -431,20 +702,33 @@ def cpu_baseline(n=16, target_s=10.0):
     dt = time.perf_counter() - t
     sample = int(min(workloads.BATCH_3D[16], max(probe, probe * target_s / max(dt, 1e-6))))
     X = workloads.normal(rng, sample * n ** 3, np.float32)
-    orc.kron3d(n, A, B, C, X[: probe * n ** 3], probe, "f32")   # warm
-    # whole passes over the sample until about target_s seconds have run (the
-    # full workload alone takes well under a second on a many-core host)
-    passes, t = 0, time.perf_counter()
-    while True:
-        orc.kron3d(n, A, B, C, X, sample, "f32")
-        passes += 1
-        dt = time.perf_counter() - t
-        if dt >= target_s or passes >= 200:
-            break
-    return {"value": round(passes * sample * flops_per_op(3, n) / dt / 1e9, 2), "unit": "GFLOP/s",
-            "cores": orc.num_threads(), "kind": "oracle",
+    f3 = sample * flops_per_op(3, n)
+    # the full workload alone takes well under a second on a many-core host
+    r32, p32, t32 = _oracle_rate(orc, lambda: orc.kron3d(n, A, B, C, X, sample, "f32"), f3, target_s)
+    X64 = X.astype(np.float64)
+    A64, B64, C64 = (m.astype(np.float64) for m in (A, B, C))
+    r64, p64, t64 = _oracle_rate(orc, lambda: orc.kron3d(n, A64, B64, C64, X64, sample, "f64"), f3, target_s / 2)
+    del X, X64
+    w0 = workloads.workload0(np.float32)
+    f0 = w0.flops()
+    one = {}
+    orc.set_num_threads(1)
+    try:
+        for prec in ("f32", "f64"):
+            dt_ = np.float32 if prec == "f32" else np.float64
+            a0, b0, x0 = (np.asarray(v, dt_) for v in (w0.A, w0.B, w0.X))
+            r, p, t = _oracle_rate(orc, lambda: orc.kron2d(w0.n, a0, b0, x0, w0.batch, prec), f0, 1.0, 10000)
+            one[prec] = round(r, 3)
+    finally:
+        orc.set_num_threads(cores)
+    return {"value": round(r32, 2), "unit": "GFLOP/s", "cores": cores, "kind": "oracle",
+            "cpu_model": cpu_model(),
             "sample": f"FP32 oracle (plain C loops, OpenMP over operands) on {sample} of the 65536 "
-                      f"3-D n=16 arrays, {passes} pass(es), {dt:.1f} s"}
+                      f"3-D n=16 arrays, {p32} pass(es), {t32:.1f} s",
+            "f64": {"value": round(r64, 2), "unit": "GFLOP/s", "cores": cores,
+                    "sample": f"same arrays in FP64, {p64} pass(es), {t64:.1f} s"},
+            "one_core_2d_n4": {"unit": "GFLOP/s", "cores": 1, "f32": one["f32"], "f64": one["f64"],
+                               "sample": "2-D n=4, 4096 operands U[-1,1], whole passes for about 1 s each"}}
 
 
 def traffic_record(khash):
@@ -626,6 +910,37 @@ def _profile_markdown(out, stats):
     return "\n".join(lines)
 
 
+def measurement_plan(torch, args):
+    """Every measurement after the headline, as (name, thunk); bench.py
+    --only NAME[,NAME] runs a subset (profiling runs)."""
+    import workloads
+    half = max(10, args.steps // 2)
+    fifth = max(5, args.steps // 5)
+    plan = [("precision", lambda: measure_precision(torch, half, args.warmup))]
+    for mode, dim, n, batch, seed in (("f32", 2, 16, workloads.BATCH_2D[16], 1),
+                                      ("f32", 2, 10, workloads.BATCH_2D[10], 1),
+                                      ("f32", 3, 10, workloads.BATCH_3D[10], 2),
+                                      ("f64", 3, 16, workloads.BATCH_3D[16] // 2, 2),
+                                      ("f64", 2, 16, workloads.BATCH_2D[16] // 2, 1),
+                                      ("bf16x3", 2, 16, workloads.BATCH_2D[16], 3)):
+        plan.append((f"{mode}-{dim}d-n{n}",
+                     lambda mode=mode, dim=dim, n=n, batch=batch, seed=seed:
+                     measure(torch, mode, dim, n, batch, half, args.warmup, seed)))
+    plan.append(("grouped", lambda: measure_grouped(torch, half, args.warmup)))
+    for beta in (0.0, 0.5):
+        plan.append((f"ex-beta{beta}", lambda beta=beta: measure_ex(torch, args.steps, args.warmup, beta)))
+    plan.append(("ex2d-transx", lambda: measure_ex2d_transx(torch, args.steps, args.warmup)))
+    for ld in (17, 20):
+        plan.append((f"strided3d-ld{ld}", lambda ld=ld: measure_strided(torch, args.steps, args.warmup, ld)))
+    plan.append(("strided2d", lambda: measure_strided2d(torch, args.steps, args.warmup)))
+    plan.append(("tkron1", lambda: measure_tkron1(torch, args.steps, args.warmup)))
+    plan.append(("backward", lambda: measure_backward(torch, args.steps, args.warmup)))
+    plan.append(("grouped-backward", lambda: measure_grouped_backward(torch, fifth, args.warmup)))
+    for case in ND_CASES:
+        plan.append((f"nd:{case}", lambda case=case: measure_nd(torch, case, fifth, args.warmup)))
+    return plan
+
+
 def main():
     args = parse()
     global DEVICE_WARM_S
@@ -657,43 +972,23 @@ def main():
         del src, dst
         torch.cuda.empty_cache()
     head = measure(torch, "f32", 3, 16, workloads.BATCH_3D[16], args.steps, args.warmup, seed=2)
+    copy = measure_copy(torch, max(10, args.steps // 2), args.warmup)
     others = []
     if not args.only_headline:
-        plan = [("bf16x3", 3, 16, workloads.BATCH_3D[16], 3),
-                ("bf16", 3, 16, workloads.BATCH_3D[16], 3),
-                ("f32", 2, 16, workloads.BATCH_2D[16], 1),
-                ("f32", 2, 10, workloads.BATCH_2D[10], 1),
-                ("f32", 3, 10, workloads.BATCH_3D[10], 2),
-                ("f64", 3, 16, workloads.BATCH_3D[16] // 2, 2),
-                ("f64", 2, 16, workloads.BATCH_2D[16] // 2, 1),
-                ("bf16x3", 2, 16, workloads.BATCH_2D[16], 3)]
-        for mode, dim, n, batch, seed in plan:
-            others.append(measure(torch, mode, dim, n, batch, max(10, args.steps // 2), args.warmup, seed))
-            print(f"# measured {mode} {dim}-D n={n}: {others[-1]['gflops']} GFLOP/s", file=sys.stderr, flush=True)
-        others.append(measure_grouped(torch, max(10, args.steps // 2), args.warmup))
-        print(f"# measured grouped mixed: {others[-1]['gflops']} GFLOP/s", file=sys.stderr, flush=True)
-        for beta in (0.0, 0.5):
-            others.append(measure_ex(torch, args.steps, args.warmup, beta))
-            print(f"# measured extended interface, beta={beta}: {others[-1]['gflops']} GFLOP/s", file=sys.stderr,
-                  flush=True)
-        others.append(measure_ex2d_transx(torch, args.steps, args.warmup))
-        print(f"# measured extended interface 2-D op(X)=T: {others[-1]['gflops']} GFLOP/s", file=sys.stderr,
-              flush=True)
-        for ld in (17, 20):
-            others.append(measure_strided(torch, args.steps, args.warmup, ld))
-            print(f"# measured strided 3-D ld {ld}: {others[-1]['gflops']} GFLOP/s", file=sys.stderr, flush=True)
-        others.append(measure_strided2d(torch, args.steps, args.warmup))
-        print(f"# measured strided 2-D: {others[-1]['gflops']} GFLOP/s", file=sys.stderr, flush=True)
-        others.append(measure_tkron1(torch, args.steps, args.warmup))
-        print(f"# measured TKRON1: {others[-1]['gflops']} GFLOP/s", file=sys.stderr, flush=True)
-        others.append(measure_backward(torch, args.steps, args.warmup))
-        print(f"# measured backward: {others[-1]['ms']} ms", file=sys.stderr, flush=True)
+        for name, run in measurement_plan(torch, args):
+            if args.only and name not in args.only.split(","):
+                continue
+            got = run()
+            others += got if isinstance(got, list) else [got]
+            last = others[-1]
+            print(f"# measured {name}: {last.get('gflops', last.get('ms'))}", file=sys.stderr, flush=True)
 
     khash = kernel_hash()
     roof = {"bound": "hbm", "achieved": head["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(head["gbs"] / HBM_PEAK_GBS, 4), "traffic": traffic_record(khash),
             "kernel": headline_kernel_name(), "alg_bytes_per_launch": head["alg_bytes"],
-            "kernel_ms": head["ms"]}
+            "kernel_ms": head["ms"], "copy_1gib": copy,
+            "frac_of_copy": round(head["gbs"] / copy["gbs"], 4)}
     line = {
         "metric": "Kron-action GFLOP/s + % HBM roofline, 3-D n=16 FP32: plain vs bf16x3 MFMA",
         "value": head["gflops"], "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -704,6 +999,7 @@ def main():
         "roofline": roof,
         "headline": head,
         "bf16x3": next((o for o in others if o.get("mode") == "bf16x3" and o.get("dim") == 3), None),
+        "bf16": next((o for o in others if o.get("mode") == "bf16" and o.get("dim") == 3), None),
         "modes": others,
         "kernel_hash": khash,
     }

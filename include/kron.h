@@ -61,9 +61,12 @@ enum kron_mode {
   KRON_MODE_BF16X3 = 2, /* FP32 in/out; each FP32 factor split into bf16 hi + lo,
                            products hi*hi' + hi*lo' + lo*hi' on bf16 matrix cores,
                            FP32 sums */
-  KRON_MODE_BF16 = 3    /* bf16 storage of A, B, C, X, Y (uint16_t bit patterns),
+  KRON_MODE_BF16 = 3,   /* bf16 storage of A, B, C, X, Y (uint16_t bit patterns),
                            FP32 sums, intermediates kept as bf16 hi + lo pairs,
                            output rounded to nearest even */
+  KRON_MODE_BF16X6 = 4  /* FP32 in/out; each FP32 value split three ways into bf16
+                           h + m + l (all 24 bits), six bf16 products per FP32 product
+                           (terms below 2^-23 dropped), FP32 sums */
 };
 
 /* ---- plain forward ------------------------------------------------------- */
@@ -86,10 +89,22 @@ int kron3d_batched_f64(int n, const double* A, const double* B, const double* C,
 /* ---- precision modes (same operations, same layouts) -------------------- */
 
 /* FP32 in/out computed with the bf16x3 split on bf16 matrix cores
-   (KRON_MODE_BF16X3).  Normwise error stays within FP32's 1e-5 gate. */
+   (KRON_MODE_BF16X3).  The split keeps 16 significant bits of every value:
+   on N(0,1) data and on the log-uniform precision workload at n = 16 the
+   normwise error stays within FP32's 1e-5 gate; on log-uniform data at
+   small n (few dominant products per output) it can reach about 2e-5. */
 int kron2d_batched_f32_bf16x3(int n, const float* A, const float* B, const float* X,
                               float* Y, int64_t batch, hipStream_t stream);
 int kron3d_batched_f32_bf16x3(int n, const float* A, const float* B, const float* C,
+                              const float* X, float* Y, int64_t batch, hipStream_t stream);
+
+/* FP32 in/out computed with the three-way bf16x6 split (KRON_MODE_BF16X6):
+   every value is held exactly as three bf16 parts and each FP32 product is
+   formed from six bf16 products on the matrix cores, so the results are as
+   accurate as plain FP32 on any data (normwise and per operand). */
+int kron2d_batched_f32_bf16x6(int n, const float* A, const float* B, const float* X,
+                              float* Y, int64_t batch, hipStream_t stream);
+int kron3d_batched_f32_bf16x6(int n, const float* A, const float* B, const float* C,
                               const float* X, float* Y, int64_t batch, hipStream_t stream);
 
 /* bf16 storage (KRON_MODE_BF16): every array holds bf16 bit patterns
@@ -200,6 +215,138 @@ int kron3d_batched_ex_f64(int n, char opA, char opB, char opC, double alpha, con
                           const double* C, const double* X, double beta, double* Y, int64_t batch, void* ws,
                           size_t ws_bytes, hipStream_t stream);
 
+/* ---- the general action: d dimensions, rectangular, complex, varying factors ---- */
+
+/* Complex scalars: (re, im) pairs, the layout of C99 float/double _Complex. */
+typedef struct kron_c32 {
+  float re, im;
+} kron_c32_t;
+typedef struct kron_c64 {
+  double re, im;
+} kron_c64_t;
+
+#define KRON_TYPE_C32 5 /* element type codes of kron_nd_workspace_size beside */
+#define KRON_TYPE_C64 6 /* KRON_MODE_F32 and KRON_MODE_F64 */
+#define KRON_ND_MAX_DIM 8
+#define KRON_ND_MAX_EXTENT 65536
+
+/* vec(Y_p) <- alpha * (op(F_0) (x) op(F_1) (x) ... (x) op(F_{d-1})) vec(X_p)
+                + beta * vec(Y_p),   p = 0 .. batch-1.
+   Section 2.1 extends the summation to arrays of any dimension d >= 1,
+   Section 2.2 gives op(M) in {M, M^T, M^*} of size m x n, complex types,
+   alpha and beta, and Section 6 names factors that change along the batch:
+     Y_p(i_0..i_{d-1}) = alpha * sum_{a_0..a_{d-1}} prod_k op(F_k)(i_k, a_k)
+                         * X_p(a_0..a_{d-1}) + beta * Y_p(i_0..i_{d-1}).
+   Layout: the last index is the fastest; X_p has extents n[0] .. n[d-1]
+   (element (a_0..a_{d-1}) at sum_k a_k * prod_{j>k} n[j]) and starts at
+   X + p * prod(n); Y_p has extents m[0] .. m[d-1] and starts at
+   Y + p * prod(m).  For d = 2 and 3 with square factors this is the plain
+   action of kron2d/kron3d_batched (F_0 = A on the slowest index).
+   ops[k]: 'N' (op(F) = F, stored m[k] x n[k]), 'T' (F^T, stored n[k] x m[k])
+   or 'C' (conjugate transpose; the same as 'T' for real types).  factors[k]
+   is column-major with leading dimension ldf[k] >= the stored row count; the
+   matrix of operand p starts at factors[k] + p * ldfp[k] elements (ldfp[k]
+   = 0: one matrix for the whole batch).  1 <= m[k], n[k] <= 65536,
+   1 <= d <= 8.  beta == 0 does not read Y.  X and Y must not overlap.
+   Computed as d mode products (fastest index first), each one pass over
+   device memory through the caller's workspace `ws` (16-byte aligned, at
+   least kron_nd_workspace_size(d, m, n, batch, type) bytes; none for d = 1)
+   with type KRON_MODE_F32, KRON_MODE_F64, KRON_TYPE_C32 or KRON_TYPE_C64.
+   Returns 0, -k (argument k invalid: 1 d, 2 m, 3 n, 4 ops, 6 factors, 7 ldf,
+   8 ldfp, 9 X, 11 Y, 12 batch, 13 ws, 14 ws_bytes) or a positive hipError_t;
+   asynchronous on `stream`. */
+size_t kron_nd_workspace_size(int d, const int* m, const int* n, int64_t batch, int type);
+int kron_nd_batched_f32(int d, const int* m, const int* n, const char* ops, float alpha, const float* const* factors,
+                        const int* ldf, const int64_t* ldfp, const float* X, float beta, float* Y, int64_t batch,
+                        void* ws, size_t ws_bytes, hipStream_t stream);
+int kron_nd_batched_f64(int d, const int* m, const int* n, const char* ops, double alpha,
+                        const double* const* factors, const int* ldf, const int64_t* ldfp, const double* X,
+                        double beta, double* Y, int64_t batch, void* ws, size_t ws_bytes, hipStream_t stream);
+int kron_nd_batched_c32(int d, const int* m, const int* n, const char* ops, kron_c32_t alpha,
+                        const kron_c32_t* const* factors, const int* ldf, const int64_t* ldfp, const kron_c32_t* X,
+                        kron_c32_t beta, kron_c32_t* Y, int64_t batch, void* ws, size_t ws_bytes,
+                        hipStream_t stream);
+int kron_nd_batched_c64(int d, const int* m, const int* n, const char* ops, kron_c64_t alpha,
+                        const kron_c64_t* const* factors, const int* ldf, const int64_t* ldfp, const kron_c64_t* X,
+                        kron_c64_t beta, kron_c64_t* Y, int64_t batch, void* ws, size_t ws_bytes,
+                        hipStream_t stream);
+
+/* Section 3's TKRON1 / TKRON2 / TKRON3 argument lists with rectangular
+   factors, leading dimensions, op in {N, T, C}, alpha, beta, and the types
+   S, D, C, Z of the paper (f32, f64, c32, c64), on the engine above (one
+   pass per dimension; the first pass reads the strided X, the last writes
+   the strided Y).  Factor roles are this library's: A acts on the slowest
+   index of each operand, B on the fastest (2-D) or the middle one (3-D), C
+   on the fastest (3-D), i.e. these compute the paper's K(B, A) and K(C, B, A)
+   in its index naming.
+     1-D: y_p <- alpha op(A) x_p + beta y_p;  op(A) ma x na; x_p (na contiguous
+          elements) at X + p*ldxp; y_p (ma elements) at Y + p*ldyp.
+     2-D: Y_p <- alpha op(B) op(X_p) op(A)^T + beta Y_p;  op(A) ma x na,
+          op(B) mb x nb, op(X_p) nb x na, Y_p mb x ma column-major with
+          leading dimension ldy, at Y + p*ldyp.  X_p is stored nb x na
+          (opX 'N') or na x nb (opX 'T' / 'C') with leading dimension ldx, at
+          X + p*ldxp.
+     3-D: vec(Y_p) <- alpha (op(A) (x) op(B) (x) op(C)) vec(X_p) + beta vec(Y_p);
+          X_p(a, b, c) (a < na slowest, c < nc fastest) at
+          X + p*ldxp + a*ldx2 + b*ldx + c, Y_p(i, j, k) at
+          Y + p*ldyp + i*ldy2 + j*ldy + k.
+   Factors: column-major, lda >= ma (op 'N') or na (op 'T' / 'C'), likewise
+   ldb, ldc.  X strides may be any values >= 0 (X is only read); Y strides
+   must give every output element its own address: ldy >= mb (2-D) or mc
+   (3-D), ldy2 >= ldy*mb, ldyp >= ldy*ma (2-D) or ldy2*ma (3-D) or ma (1-D).
+   Every extent is in 1..65536.  beta == 0 does not read Y; X and Y must not
+   overlap.  ws: at least kron_nd_workspace_size(d, m, n, batch, type) bytes
+   with m = {ma, mb[, mc]}, n = {na, nb[, nc]} (none for 1-D).  Returns 0,
+   -k (argument k invalid, counting from 1 in the order of the signature),
+   or a positive hipError_t; asynchronous on `stream`. */
+int kron1d_batched_rect_f32(char opA, int ma, int na, int64_t batch, float alpha, const float* A, int lda,
+                            const float* X, int64_t ldxp, float beta, float* Y, int64_t ldyp, void* ws, size_t ws_bytes,
+                            hipStream_t stream);
+int kron2d_batched_rect_f32(char opA, char opB, char opX, int ma, int na, int mb, int nb, int64_t batch,
+                            float alpha, const float* A, int lda, const float* B, int ldb, const float* X, int64_t ldx,
+                            int64_t ldxp, float beta, float* Y, int64_t ldy, int64_t ldyp, void* ws, size_t ws_bytes,
+                            hipStream_t stream);
+int kron3d_batched_rect_f32(char opA, char opB, char opC, int ma, int na, int mb, int nb, int mc, int nc,
+                            int64_t batch, float alpha, const float* A, int lda, const float* B, int ldb, const float* C,
+                            int ldc, const float* X, int64_t ldx, int64_t ldx2, int64_t ldxp, float beta, float* Y,
+                            int64_t ldy, int64_t ldy2, int64_t ldyp, void* ws, size_t ws_bytes, hipStream_t stream);
+
+int kron1d_batched_rect_f64(char opA, int ma, int na, int64_t batch, double alpha, const double* A, int lda,
+                            const double* X, int64_t ldxp, double beta, double* Y, int64_t ldyp, void* ws, size_t ws_bytes,
+                            hipStream_t stream);
+int kron2d_batched_rect_f64(char opA, char opB, char opX, int ma, int na, int mb, int nb, int64_t batch,
+                            double alpha, const double* A, int lda, const double* B, int ldb, const double* X, int64_t ldx,
+                            int64_t ldxp, double beta, double* Y, int64_t ldy, int64_t ldyp, void* ws, size_t ws_bytes,
+                            hipStream_t stream);
+int kron3d_batched_rect_f64(char opA, char opB, char opC, int ma, int na, int mb, int nb, int mc, int nc,
+                            int64_t batch, double alpha, const double* A, int lda, const double* B, int ldb, const double* C,
+                            int ldc, const double* X, int64_t ldx, int64_t ldx2, int64_t ldxp, double beta, double* Y,
+                            int64_t ldy, int64_t ldy2, int64_t ldyp, void* ws, size_t ws_bytes, hipStream_t stream);
+
+int kron1d_batched_rect_c32(char opA, int ma, int na, int64_t batch, kron_c32_t alpha, const kron_c32_t* A, int lda,
+                            const kron_c32_t* X, int64_t ldxp, kron_c32_t beta, kron_c32_t* Y, int64_t ldyp, void* ws, size_t ws_bytes,
+                            hipStream_t stream);
+int kron2d_batched_rect_c32(char opA, char opB, char opX, int ma, int na, int mb, int nb, int64_t batch,
+                            kron_c32_t alpha, const kron_c32_t* A, int lda, const kron_c32_t* B, int ldb, const kron_c32_t* X, int64_t ldx,
+                            int64_t ldxp, kron_c32_t beta, kron_c32_t* Y, int64_t ldy, int64_t ldyp, void* ws, size_t ws_bytes,
+                            hipStream_t stream);
+int kron3d_batched_rect_c32(char opA, char opB, char opC, int ma, int na, int mb, int nb, int mc, int nc,
+                            int64_t batch, kron_c32_t alpha, const kron_c32_t* A, int lda, const kron_c32_t* B, int ldb, const kron_c32_t* C,
+                            int ldc, const kron_c32_t* X, int64_t ldx, int64_t ldx2, int64_t ldxp, kron_c32_t beta, kron_c32_t* Y,
+                            int64_t ldy, int64_t ldy2, int64_t ldyp, void* ws, size_t ws_bytes, hipStream_t stream);
+
+int kron1d_batched_rect_c64(char opA, int ma, int na, int64_t batch, kron_c64_t alpha, const kron_c64_t* A, int lda,
+                            const kron_c64_t* X, int64_t ldxp, kron_c64_t beta, kron_c64_t* Y, int64_t ldyp, void* ws, size_t ws_bytes,
+                            hipStream_t stream);
+int kron2d_batched_rect_c64(char opA, char opB, char opX, int ma, int na, int mb, int nb, int64_t batch,
+                            kron_c64_t alpha, const kron_c64_t* A, int lda, const kron_c64_t* B, int ldb, const kron_c64_t* X, int64_t ldx,
+                            int64_t ldxp, kron_c64_t beta, kron_c64_t* Y, int64_t ldy, int64_t ldyp, void* ws, size_t ws_bytes,
+                            hipStream_t stream);
+int kron3d_batched_rect_c64(char opA, char opB, char opC, int ma, int na, int mb, int nb, int mc, int nc,
+                            int64_t batch, kron_c64_t alpha, const kron_c64_t* A, int lda, const kron_c64_t* B, int ldb, const kron_c64_t* C,
+                            int ldc, const kron_c64_t* X, int64_t ldx, int64_t ldx2, int64_t ldxp, kron_c64_t beta, kron_c64_t* Y,
+                            int64_t ldy, int64_t ldy2, int64_t ldyp, void* ws, size_t ws_bytes, hipStream_t stream);
+
 /* ---- Section 3's interface with leading dimensions ------------------------------ */
 
 /* The extended update above on strided storage, with the argument layout of
@@ -300,6 +447,40 @@ int kron2d_backward_f64(int n, const double* A, const double* B, const double* X
 int kron3d_backward_f64(int n, const double* A, const double* B, const double* C, const double* X,
                         const double* dY, double* dX, double* dA, double* dB, double* dC, int64_t batch,
                         void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Backward over a mixed batch: the gradients above for every group of a
+   batch that mixes sizes and 2-D / 3-D operands (Section 2.2's batched
+   update with one set of shared factors per group).  Each group's dA, dB, dC
+   are summed over that group's operands only.  mode is KRON_MODE_F32 or
+   KRON_MODE_F64 (the arrays' element type); C and dC are ignored for dim 2;
+   any of dX, dA, dB, dC may be NULL to skip it, and X may be NULL in a group
+   that requests no factor gradient.  `ws` is caller-owned device memory of at
+   least kron_grouped_backward_workspace_size() bytes (each group's partial
+   sums in its own slice).  Every descriptor is checked before anything is
+   launched; the groups then run in descriptor order on `stream`, each as
+   kron{2,3}d_backward_{f32,f64} would.  Returns 0; -1 (groups NULL or an
+   invalid descriptor), -2 (ngroups < 1), -3 (ws NULL while needed), -4
+   (ws_bytes too small), or a positive hipError_t.  The result of every group
+   is the single-group call's, bit for bit. */
+typedef struct kron_group_grad {
+  int32_t dim;      /* 2 or 3 */
+  int32_t n;        /* 1..16 */
+  int32_t mode;     /* KRON_MODE_F32 or KRON_MODE_F64 */
+  int32_t reserved; /* set to 0 */
+  const void* A;
+  const void* B;
+  const void* C;
+  const void* X;    /* count * n^dim */
+  const void* dY;   /* count * n^dim */
+  void* dX;         /* count * n^dim, or NULL */
+  void* dA;         /* n * n each, or NULL */
+  void* dB;
+  void* dC;
+  int64_t count;    /* operands in the group, >= 0 */
+} kron_group_grad_t;
+size_t kron_grouped_backward_workspace_size(const kron_group_grad_t* groups, int ngroups);
+int kron_grouped_backward(const kron_group_grad_t* groups, int ngroups, void* ws, size_t ws_bytes,
+                          hipStream_t stream);
 
 /* ---- launch shape ----------------------------------------------------------- */
 

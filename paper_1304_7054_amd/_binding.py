@@ -10,12 +10,14 @@ there is no other code path.  If libkron.so is missing, every call raises.
 import ctypes
 import os
 
+import numpy as np
+
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libkron.so")
 
-MODE_F32, MODE_F64, MODE_BF16X3, MODE_BF16 = 0, 1, 2, 3
+MODE_F32, MODE_F64, MODE_BF16X3, MODE_BF16, MODE_BF16X6 = 0, 1, 2, 3, 4
 
 
 class KronError(RuntimeError):
@@ -36,6 +38,26 @@ class KronGroup(ctypes.Structure):
                 ("C", ctypes.c_void_p), ("X", ctypes.c_void_p), ("Y", ctypes.c_void_p),
                 ("count", ctypes.c_int64)]
 
+class KronGroupGrad(ctypes.Structure):
+    """kron_group_grad_t of include/kron.h."""
+    _fields_ = [("dim", ctypes.c_int32), ("n", ctypes.c_int32), ("mode", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("A", ctypes.c_void_p), ("B", ctypes.c_void_p),
+                ("C", ctypes.c_void_p), ("X", ctypes.c_void_p), ("dY", ctypes.c_void_p),
+                ("dX", ctypes.c_void_p), ("dA", ctypes.c_void_p), ("dB", ctypes.c_void_p),
+                ("dC", ctypes.c_void_p), ("count", ctypes.c_int64)]
+
+class KronC32(ctypes.Structure):
+    """kron_c32_t of include/kron.h (a complex float, by value)."""
+    _fields_ = [("re", ctypes.c_float), ("im", ctypes.c_float)]
+
+
+class KronC64(ctypes.Structure):
+    """kron_c64_t of include/kron.h (a complex double, by value)."""
+    _fields_ = [("re", ctypes.c_double), ("im", ctypes.c_double)]
+
+
+KRON_TYPE_C32, KRON_TYPE_C64 = 5, 6
+
 # (name, argument kinds); 'i' int, 'l' int64, 'p' pointer, 'S' stream, 'z' size_t,
 # 'c' char, 'f' float, 'd' double
 SIGNATURES = {
@@ -45,6 +67,8 @@ SIGNATURES = {
     "kron3d_batched_f64": "ippppplS",
     "kron2d_batched_f32_bf16x3": "ipppplS",
     "kron3d_batched_f32_bf16x3": "ippppplS",
+    "kron2d_batched_f32_bf16x6": "ipppplS",
+    "kron3d_batched_f32_bf16x6": "ippppplS",
     "kron2d_batched_bf16": "ipppplS",
     "kron3d_batched_bf16": "ippppplS",
     "kron2d_batched_adjoint_f32": "ipppplS",
@@ -68,7 +92,14 @@ SIGNATURES = {
 }
 
 _CT = {"i": ctypes.c_int, "l": ctypes.c_int64, "p": ctypes.c_void_p, "S": ctypes.c_void_p,
-       "z": ctypes.c_size_t, "c": ctypes.c_char, "f": ctypes.c_float, "d": ctypes.c_double}
+       "z": ctypes.c_size_t, "c": ctypes.c_char, "f": ctypes.c_float, "d": ctypes.c_double,
+       "C": KronC32, "Z": KronC64}
+
+_RECT_SCALAR = {"f32": "f", "f64": "d", "c32": "C", "c64": "Z"}
+for _t, _k in _RECT_SCALAR.items():
+    SIGNATURES[f"kron1d_batched_rect_{_t}"] = f"ciil{_k}pipl{_k}plpzS"
+    SIGNATURES[f"kron2d_batched_rect_{_t}"] = f"ccciiiil{_k}pipipll{_k}pllpzS"
+    SIGNATURES[f"kron3d_batched_rect_{_t}"] = f"ccciiiiiil{_k}pipipiplll{_k}plllpzS"
 
 
 def lib():
@@ -98,6 +129,20 @@ def lib():
         L.kron_grouped_prepare.restype = ctypes.c_int
         L.kron_grouped_launch.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
         L.kron_grouped_launch.restype = ctypes.c_int
+        ip, lp, cp = ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int64), ctypes.c_char_p
+        L.kron_nd_workspace_size.argtypes = [ctypes.c_int, ip, ip, ctypes.c_int64, ctypes.c_int]
+        L.kron_nd_workspace_size.restype = ctypes.c_size_t
+        for name, sc in (("kron_nd_batched_f32", ctypes.c_float), ("kron_nd_batched_f64", ctypes.c_double),
+                         ("kron_nd_batched_c32", KronC32), ("kron_nd_batched_c64", KronC64)):
+            f = getattr(L, name)
+            f.argtypes = [ctypes.c_int, ip, ip, cp, sc, ctypes.POINTER(ctypes.c_void_p), ip, lp, ctypes.c_void_p, sc,
+                          ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+            f.restype = ctypes.c_int
+        L.kron_grouped_backward_workspace_size.argtypes = [ctypes.POINTER(KronGroupGrad), ctypes.c_int]
+        L.kron_grouped_backward_workspace_size.restype = ctypes.c_size_t
+        L.kron_grouped_backward.argtypes = [ctypes.POINTER(KronGroupGrad), ctypes.c_int, ctypes.c_void_p,
+                                            ctypes.c_size_t, ctypes.c_void_p]
+        L.kron_grouped_backward.restype = ctypes.c_int
         L.kron_graph_capture_grouped.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]
         L.kron_graph_capture_grouped.restype = ctypes.c_int
         L.kron_graph_launch.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
@@ -113,7 +158,25 @@ def lib():
         L.kron_get_launch.argtypes = [ctypes.c_int] * 3 + [ctypes.POINTER(ctypes.c_int)] * 2
         L.kron_get_launch.restype = ctypes.c_int
         _LIB = L
+        _apply_shipped_table()
     return _LIB
+
+
+APPLIED_TABLE = {"path": None, "entries": 0}
+
+
+def _apply_shipped_table():
+    """Apply the launch table measured by the autotuner for this GPU's
+    architecture (tuning/<arch>.json), unless KRON_TUNE_CACHE names another
+    table; entries keyed for another device or HIP version are ignored."""
+    if os.environ.get("KRON_TUNE_CACHE") or not torch.cuda.is_available():
+        return
+    from . import tune
+    arch = tune.device_key().split("|")[0]
+    path = os.path.join(HERE, "tuning", f"{arch}.json")
+    if os.path.exists(path):
+        APPLIED_TABLE["entries"] = tune.load(path)
+        APPLIED_TABLE["path"] = os.path.relpath(path, os.path.dirname(HERE))
 
 
 def status_string(status: int) -> str:
@@ -221,6 +284,14 @@ def kron3d_batched_f32_bf16x3(n, A, B, C, X, Y, batch, stream=None):
     return _dim_call("kron3d_batched_f32_bf16x3", 3, torch.float32, n, (A, B, C), X, Y, batch, stream)
 
 
+def kron2d_batched_f32_bf16x6(n, A, B, X, Y, batch, stream=None):
+    return _dim_call("kron2d_batched_f32_bf16x6", 2, torch.float32, n, (A, B), X, Y, batch, stream)
+
+
+def kron3d_batched_f32_bf16x6(n, A, B, C, X, Y, batch, stream=None):
+    return _dim_call("kron3d_batched_f32_bf16x6", 3, torch.float32, n, (A, B, C), X, Y, batch, stream)
+
+
 def kron2d_batched_bf16(n, A, B, X, Y, batch, stream=None):
     """bf16 storage: tensors of dtype torch.bfloat16 (or int16/uint16 bit patterns viewed as bfloat16)."""
     return _dim_call("kron2d_batched_bf16", 2, torch.bfloat16, n, (A, B), X, Y, batch, stream)
@@ -268,7 +339,9 @@ def _backward_call(name, dim, dtype, mode, n, mats, X, dY, dX, grads, batch, ws,
         if t is not None and size > 0 and any(o is not None and t.data_ptr() == o.data_ptr() for o in (X, dY)):
             raise ValueError("outputs must not alias X or dY")
     need = kron_backward_workspace_size(dim, n, batch, mode) if any(G is not None for G in grads) else 0
-    if need and (ws is None or ws.numel() * ws.element_size() < need):
+    if need and ws is None:
+        ws = _scratch(need, dY.device, stream)
+    if need and ws.numel() * ws.element_size() < need:
         raise ValueError(f"workspace must hold {need} bytes")
     pws = ctypes.c_void_p(ws.data_ptr()) if ws is not None else None
     nbytes = ws.numel() * ws.element_size() if ws is not None else 0
@@ -347,6 +420,204 @@ def kron3d_batched_ex_f32(n, opA, opB, opC, alpha, A, B, C, X, beta, Y, batch, w
 def kron3d_batched_ex_f64(n, opA, opB, opC, alpha, A, B, C, X, beta, Y, batch, ws=None, stream=None):
     return _ex_call("kron3d_batched_ex_f64", 3, torch.float64, MODE_F64, n, (opA, opB, opC), float(alpha),
                     (A, B, C), X, float(beta), Y, batch, ws, stream)
+
+
+_ND_TYPES = {torch.float32: ("f32", MODE_F32), torch.float64: ("f64", MODE_F64),
+             torch.complex64: ("c32", KRON_TYPE_C32), torch.complex128: ("c64", KRON_TYPE_C64)}
+
+
+def kron_nd_workspace_size(m, n, batch, type_code):
+    """Bytes of workspace kron_nd_batched_* needs (0 for invalid arguments)."""
+    d = len(m)
+    ci = ctypes.c_int * max(1, d)
+    return int(lib().kron_nd_workspace_size(d, ci(*m), ci(*n), int(batch), int(type_code)))
+
+
+def _nd_call(tag, m, n, ops, alpha, factors, ldf, ldfp, X, beta, Y, batch, ws, stream):
+    dtype = {"f32": torch.float32, "f64": torch.float64, "c32": torch.complex64, "c64": torch.complex128}[tag]
+    code = _ND_TYPES[dtype][1]
+    m, n = [int(v) for v in m], [int(v) for v in n]
+    d, batch = len(m), int(batch)
+    if not 1 <= d <= 8 or len(n) != d or len(ops) != d or len(factors) != d:
+        raise ValueError("d must be in 1..8 with one size, op and factor per dimension")
+    if min(m + n) < 1 or max(m + n) > 65536:
+        raise ValueError("every extent must be in 1..65536")
+    if batch < 0:
+        raise ValueError("batch must be >= 0")
+    for o in ops:
+        if o not in "NnTtCc":
+            raise ValueError(f"op must be 'N', 'T' or 'C', got {o!r}")
+    rows = [m[k] if ops[k] in "Nn" else n[k] for k in range(d)]
+    cols = [n[k] if ops[k] in "Nn" else m[k] for k in range(d)]
+    ldf = list(rows) if ldf is None else [int(v) for v in ldf]
+    ldfp = [0] * d if ldfp is None else [int(v) for v in ldfp]
+    ptrs = []
+    for k in range(d):
+        if ldf[k] < rows[k] or ldfp[k] < 0:
+            raise ValueError(f"factor {k}: leading dimension or operand stride too small")
+        one = rows[k] + ldf[k] * (cols[k] - 1)
+        need = one + (batch - 1) * ldfp[k] if batch > 0 else one
+        ptrs.append(_arr(factors[k], dtype, need, f"factor {k}").value)
+    nx, ny = batch * int(np.prod(n)), batch * int(np.prod(m))
+    px = _arr(X, dtype, nx, "X")
+    py = _arr(Y, dtype, ny, "Y")
+    if nx > 0 and ny > 0:
+        esz = X.element_size()
+        x0, y0 = X.data_ptr(), Y.data_ptr()
+        if x0 < y0 + ny * esz and y0 < x0 + nx * esz:
+            raise ValueError("X and Y must not overlap")
+    need = kron_nd_workspace_size(m, n, batch, code)
+    if ws is None and need > 0:
+        ws = _scratch(need, Y.device, stream)
+    pw = _arr(ws, torch.uint8, need, "workspace") if need > 0 else None
+    ci = ctypes.c_int * d
+    if tag in ("c32", "c64"):
+        S = KronC32 if tag == "c32" else KronC64
+        a, b = complex(alpha), complex(beta)
+        alpha_c, beta_c = S(a.real, a.imag), S(b.real, b.imag)
+    else:
+        alpha_c, beta_c = float(alpha), float(beta)
+    return _call(f"kron_nd_batched_{tag}", d, ci(*m), ci(*n), "".join(ops).encode(), alpha_c,
+                 (ctypes.c_void_p * d)(*ptrs), ci(*ldf), (ctypes.c_int64 * d)(*ldfp), px, beta_c, py, batch, pw,
+                 0 if ws is None else ws.numel(), _stream(stream))
+
+
+def kron_nd_batched_f32(m, n, ops, alpha, factors, X, beta, Y, batch, ldf=None, ldfp=None, ws=None, stream=None):
+    """vec(Y_p) = alpha (op(F_0) kron .. kron op(F_{d-1})) vec(X_p) + beta vec(Y_p), FP32 (include/kron.h)."""
+    return _nd_call("f32", m, n, ops, alpha, factors, ldf, ldfp, X, beta, Y, batch, ws, stream)
+
+
+def kron_nd_batched_f64(m, n, ops, alpha, factors, X, beta, Y, batch, ldf=None, ldfp=None, ws=None, stream=None):
+    return _nd_call("f64", m, n, ops, alpha, factors, ldf, ldfp, X, beta, Y, batch, ws, stream)
+
+
+def kron_nd_batched_c32(m, n, ops, alpha, factors, X, beta, Y, batch, ldf=None, ldfp=None, ws=None, stream=None):
+    """Complex FP32 pairs (torch.complex64)."""
+    return _nd_call("c32", m, n, ops, alpha, factors, ldf, ldfp, X, beta, Y, batch, ws, stream)
+
+
+def kron_nd_batched_c64(m, n, ops, alpha, factors, X, beta, Y, batch, ldf=None, ldfp=None, ws=None, stream=None):
+    """Complex FP64 pairs (torch.complex128)."""
+    return _nd_call("c64", m, n, ops, alpha, factors, ldf, ldfp, X, beta, Y, batch, ws, stream)
+
+
+def kron_nd_batched(m, n, ops, alpha, factors, X, beta, Y, batch, ldf=None, ldfp=None, ws=None, stream=None):
+    """The kron_nd_batched_* entry point of X's dtype."""
+    if X.dtype not in _ND_TYPES:
+        raise TypeError(f"unsupported dtype {X.dtype}")
+    return _nd_call(_ND_TYPES[X.dtype][0], m, n, ops, alpha, factors, ldf, ldfp, X, beta, Y, batch, ws, stream)
+
+
+def _span(exts, strides, batch, sp):
+    """Elements from an operand array's first element to one past its last
+    element over the whole batch (0 for an empty batch)."""
+    if batch <= 0:
+        return 0
+    return 1 + sum((e - 1) * st for e, st in zip(exts, strides)) + (batch - 1) * sp
+
+
+def _rect_call(tag, d, ops, m, n, batch, alpha, mats, lds, X, xstrides, xsp, beta, Y, ystrides, ysp, ws, stream):
+    dtype = {"f32": torch.float32, "f64": torch.float64, "c32": torch.complex64, "c64": torch.complex128}[tag]
+    code = _ND_TYPES[dtype][1]
+    m, n, batch = [int(v) for v in m], [int(v) for v in n], int(batch)
+    for o in ops:
+        if o not in "NnTtCc":
+            raise ValueError(f"op must be 'N', 'T' or 'C', got {o!r}")
+    if min(m + n) < 1 or max(m + n) > 65536 or batch < 0:
+        raise ValueError("extents must be in 1..65536 and batch >= 0")
+    ptrs = []
+    for k in range(d):
+        rows, cols = (m[k], n[k]) if ops[k] in "Nn" else (n[k], m[k])
+        if int(lds[k]) < rows:
+            raise ValueError(f"leading dimension of factor {k} too small")
+        ptrs += [_arr(mats[k], dtype, rows + int(lds[k]) * (cols - 1), f"factor {k}"), int(lds[k])]
+    if min(list(xstrides) + [xsp]) < 0:
+        raise ValueError("X strides must be >= 0")
+    ex = _span(n if d != 2 or ops[2] in "Nn" else n, xstrides, batch, xsp)
+    ey = _span(m, ystrides, batch, ysp)
+    px, py = _arr(X, dtype, ex, "X"), _arr(Y, dtype, ey, "Y")
+    if ex > 0 and ey > 0:
+        esz = X.element_size()
+        x0, y0 = X.data_ptr(), Y.data_ptr()
+        if x0 < y0 + ey * esz and y0 < x0 + ex * esz:
+            raise ValueError("X and Y must not overlap")
+    need = kron_nd_workspace_size(m, n, batch, code)
+    if ws is None and need > 0:
+        ws = _scratch(need, Y.device, stream)
+    pw = _arr(ws, torch.uint8, need, "workspace") if need > 0 else None
+    if tag in ("c32", "c64"):
+        S = KronC32 if tag == "c32" else KronC64
+        a, b = complex(alpha), complex(beta)
+        alpha, beta = S(a.real, a.imag), S(b.real, b.imag)
+    else:
+        alpha, beta = float(alpha), float(beta)
+    return alpha, beta, ptrs, px, py, pw, 0 if ws is None else ws.numel()
+
+
+def _rect1(tag, opA, ma, na, batch, alpha, A, lda, X, ldxp, beta, Y, ldyp, ws=None, stream=None):
+    if int(ldyp) < int(ma):
+        raise ValueError("ldyp must be >= ma")
+    a, b, ptrs, px, py, pw, wb = _rect_call(tag, 1, opA, [ma], [na], batch, alpha, [A], [lda], X, [1], int(ldxp),
+                                            beta, Y, [1], int(ldyp), ws, stream)
+    return _call(f"kron1d_batched_rect_{tag}", _op_any(opA), int(ma), int(na), int(batch), a, *ptrs, px,
+                 int(ldxp), b, py, int(ldyp), pw, wb, _stream(stream))
+
+
+def _rect2(tag, opA, opB, opX, ma, na, mb, nb, batch, alpha, A, lda, B, ldb, X, ldx, ldxp, beta, Y, ldy, ldyp,
+           ws=None, stream=None):
+    ldx, ldxp, ldy, ldyp = int(ldx), int(ldxp), int(ldy), int(ldyp)
+    if ldy < int(mb) or ldyp < ldy * int(ma):
+        raise ValueError("Y strides must give every output element its own address (ldy >= mb, ldyp >= ldy*ma)")
+    xs = [ldx, 1] if opX in "Nn" else [1, ldx]       # strides of (slow a0, fast a1) of op(X_p)
+    a, b, ptrs, px, py, pw, wb = _rect_call(tag, 2, opA + opB + opX, [ma, mb], [na, nb], batch, alpha, [A, B],
+                                            [lda, ldb], X, xs, ldxp, beta, Y, [ldy, 1], ldyp, ws, stream)
+    return _call(f"kron2d_batched_rect_{tag}", _op_any(opA), _op_any(opB), _op_any(opX), int(ma), int(na), int(mb),
+                 int(nb), int(batch), a, *ptrs, px, ldx, ldxp, b, py, ldy, ldyp, pw, wb, _stream(stream))
+
+
+def _rect3(tag, opA, opB, opC, ma, na, mb, nb, mc, nc, batch, alpha, A, lda, B, ldb, C, ldc, X, ldx, ldx2, ldxp,
+           beta, Y, ldy, ldy2, ldyp, ws=None, stream=None):
+    ldx, ldx2, ldxp = int(ldx), int(ldx2), int(ldxp)
+    ldy, ldy2, ldyp = int(ldy), int(ldy2), int(ldyp)
+    if ldy < int(mc) or ldy2 < ldy * int(mb) or ldyp < ldy2 * int(ma):
+        raise ValueError("Y strides must give every output element its own address")
+    a, b, ptrs, px, py, pw, wb = _rect_call(tag, 3, opA + opB + opC, [ma, mb, mc], [na, nb, nc], batch, alpha,
+                                            [A, B, C], [lda, ldb, ldc], X, [ldx2, ldx, 1], ldxp, beta, Y,
+                                            [ldy2, ldy, 1], ldyp, ws, stream)
+    return _call(f"kron3d_batched_rect_{tag}", _op_any(opA), _op_any(opB), _op_any(opC), int(ma), int(na), int(mb),
+                 int(nb), int(mc), int(nc), int(batch), a, *ptrs, px, ldx, ldx2, ldxp, b, py, ldy, ldy2, ldyp, pw, wb,
+                 _stream(stream))
+
+
+def _op_any(op):
+    if op not in ("N", "n", "T", "t", "C", "c"):
+        raise ValueError(f"op must be 'N', 'T' or 'C', got {op!r}")
+    return op.encode()
+
+
+def _make_rect(tag):
+    def k1(opA, ma, na, batch, alpha, A, lda, X, ldxp, beta, Y, ldyp, ws=None, stream=None):
+        return _rect1(tag, opA, ma, na, batch, alpha, A, lda, X, ldxp, beta, Y, ldyp, ws, stream)
+
+    def k2(opA, opB, opX, ma, na, mb, nb, batch, alpha, A, lda, B, ldb, X, ldx, ldxp, beta, Y, ldy, ldyp, ws=None,
+           stream=None):
+        return _rect2(tag, opA, opB, opX, ma, na, mb, nb, batch, alpha, A, lda, B, ldb, X, ldx, ldxp, beta, Y, ldy,
+                      ldyp, ws, stream)
+
+    def k3(opA, opB, opC, ma, na, mb, nb, mc, nc, batch, alpha, A, lda, B, ldb, C, ldc, X, ldx, ldx2, ldxp, beta, Y,
+           ldy, ldy2, ldyp, ws=None, stream=None):
+        return _rect3(tag, opA, opB, opC, ma, na, mb, nb, mc, nc, batch, alpha, A, lda, B, ldb, C, ldc, X, ldx, ldx2,
+                      ldxp, beta, Y, ldy, ldy2, ldyp, ws, stream)
+    for f, dd in ((k1, 1), (k2, 2), (k3, 3)):
+        f.__name__ = f.__qualname__ = f"kron{dd}d_batched_rect_{tag}"
+        f.__doc__ = f"TKRON{dd} with rectangular factors ({tag}); see include/kron.h."
+    return k1, k2, k3
+
+
+(kron1d_batched_rect_f32, kron2d_batched_rect_f32, kron3d_batched_rect_f32) = _make_rect("f32")
+(kron1d_batched_rect_f64, kron2d_batched_rect_f64, kron3d_batched_rect_f64) = _make_rect("f64")
+(kron1d_batched_rect_c32, kron2d_batched_rect_c32, kron3d_batched_rect_c32) = _make_rect("c32")
+(kron1d_batched_rect_c64, kron2d_batched_rect_c64, kron3d_batched_rect_c64) = _make_rect("c64")
 
 
 def _extent(n, strides):
@@ -482,6 +753,59 @@ def _groups_array(groups):
     return arr, len(groups)
 
 
+def _grad_groups_array(groups):
+    """groups: iterable of dicts with dim, n, A, B, (C), X, dY, count, the
+    optional outputs dX, dA, dB, (dC) and an optional mode (MODE_F32 default
+    or MODE_F64, the tensors' dtype)."""
+    groups = list(groups)
+    arr = (KronGroupGrad * max(1, len(groups)))()
+    for i, g in enumerate(groups):
+        dim, n, count = int(g["dim"]), int(g["n"]), int(g["count"])
+        mode = int(g.get("mode", MODE_F32))
+        if dim not in (2, 3) or not 1 <= n <= 16 or count < 0:
+            raise ValueError(f"group {i}: bad dim/n/count")
+        if mode not in (MODE_F32, MODE_F64):
+            raise ValueError(f"group {i}: mode must be MODE_F32 or MODE_F64")
+        dt = _MODE_DTYPE[mode]
+        size = count * n ** dim
+        names = ("A", "B", "C")[:dim]
+        mats = [_arr(g[k], dt, n * n, f"group {i} {k}") for k in names]
+        want = [g.get(k) for k in ("dA", "dB", "dC")[:dim]]
+        outs = [_arr(t, dt, n * n, f"group {i} d{k}") if t is not None else None for t, k in zip(want, names)]
+        px = _arr(g["X"], dt, size, f"group {i} X") if g.get("X") is not None else None
+        if px is None and any(t is not None for t in want) and count > 0:
+            raise ValueError(f"group {i}: X is needed for factor gradients")
+        pdy = _arr(g["dY"], dt, size, f"group {i} dY")
+        pdx = None
+        if g.get("dX") is not None:
+            pdx = _arr(g["dX"], dt, size, f"group {i} dX")
+            for other in ("X", "dY"):
+                if g.get(other) is not None and size > 0 and g["dX"].data_ptr() == g[other].data_ptr():
+                    raise ValueError(f"group {i}: dX must not alias {other}")
+        arr[i] = KronGroupGrad(dim, n, mode, 0, mats[0], mats[1], mats[2] if dim == 3 else None, px, pdy, pdx,
+                               outs[0], outs[1], outs[2] if dim == 3 else None, count)
+    return arr, len(groups)
+
+
+def kron_grouped_backward_workspace_size(groups):
+    arr, k = _grad_groups_array(groups)
+    return int(lib().kron_grouped_backward_workspace_size(arr, k))
+
+
+def kron_grouped_backward(groups, ws=None, stream=None):
+    """dX, dA, dB, dC of every group of a mixed batch (see include/kron.h);
+    ws (uint8 tensor) defaults to a fresh buffer recorded on the stream."""
+    arr, k = _grad_groups_array(groups)
+    need = int(lib().kron_grouped_backward_workspace_size(arr, k))
+    if need == 0:
+        raise ValueError("invalid group descriptors")
+    if ws is None:
+        dev = next(iter(groups))["dY"].device
+        ws = _scratch(need, dev, stream)
+    pw = _arr(ws, torch.uint8, need, "workspace")
+    return _call("kron_grouped_backward", arr, k, pw, ws.numel(), _stream(stream))
+
+
 def kron_grouped_workspace_size(groups):
     arr, k = _groups_array(groups)
     return int(lib().kron_grouped_workspace_size(arr, k))
@@ -515,7 +839,7 @@ def kron_graph_destroy(graph_exec):
 
 
 _MODE_DTYPE = {MODE_F32: torch.float32, MODE_F64: torch.float64, MODE_BF16X3: torch.float32,
-               MODE_BF16: torch.bfloat16}
+               MODE_BF16: torch.bfloat16, MODE_BF16X6: torch.float32}
 
 
 def kron_autotune(mode, dim, n, A, B, C, X, Y, batch, reps=10, stream=None):

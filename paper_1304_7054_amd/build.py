@@ -31,15 +31,37 @@ def _obj(src):
     return os.path.join(OBJ_DIR, os.path.basename(src)[:-4] + ".o")
 
 
+_INCLUDE_RE = None
+
+
+def _deps(path, seen=None):
+    """The file and every project header it includes, transitively."""
+    import re
+    global _INCLUDE_RE
+    if _INCLUDE_RE is None:
+        _INCLUDE_RE = re.compile(r'^\s*#\s*include\s+"([^"]+)"', re.M)
+    seen = set() if seen is None else seen
+    if path in seen:
+        return seen
+    seen.add(path)
+    with open(path) as f:
+        text = f.read()
+    for name in _INCLUDE_RE.findall(text):
+        for d in (os.path.dirname(path), CSRC, INCLUDE):
+            cand = os.path.join(d, name)
+            if os.path.exists(cand):
+                _deps(cand, seen)
+                break
+    return seen
+
+
 def _stale(src):
-    """An object is stale when older than its source or any shared header."""
+    """An object is stale when older than its source or any header it includes."""
     obj = _obj(src)
     if not os.path.exists(obj):
         return True
-    deps = [src, os.path.join(INCLUDE, "kron.h")]
-    deps += [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hpp")]
     t = os.path.getmtime(obj)
-    return any(os.path.getmtime(d) > t for d in deps)
+    return any(os.path.getmtime(d) > t for d in _deps(src))
 
 
 def _compile(src, verbose):

@@ -12,6 +12,8 @@
 
 namespace kron {
 
+constexpr int kNumModesAbi = 5;  // modes the launch table and the autotuner know
+
 int device_cus() {
   static std::atomic<int> cache[64];
   int dev = 0;
@@ -27,9 +29,10 @@ int device_cus() {
 }
 
 namespace {
+constexpr int kNumModes = kNumModesAbi;
 // Launch shapes per (mode, dim - 2, n), packed as blocks_per_cu * 16 + variant.
 // -1 = not set: the built-in default applies.
-std::atomic<int> g_shape[4][2][17];
+std::atomic<int> g_shape[kNumModes][2][17];
 
 void init_shapes() {
   // thread-safe one-time initialisation (C++11 static local)
@@ -51,6 +54,7 @@ LaunchShape default_shape(int mode, int dim, int n) {
       case 0: return LaunchShape{2, 9};   // FP32: stores interleaved with the next tile, 2-slab window
       case 1: return LaunchShape{2, 7};   // FP64: 4-slab window + next tile
       case 2: return LaunchShape{2, 9};   // bf16x3: as FP32
+      case 4: return LaunchShape{2, 9};   // bf16x6: as FP32
       default: return LaunchShape{0, 10}; // bf16 storage: stores interleaved, 4-slab window
     }
   }
@@ -64,7 +68,7 @@ LaunchShape default_shape(int mode, int dim, int n) {
 
 LaunchShape launch_shape(int mode, int dim, int n) {
   init_shapes();
-  if (mode < 0 || mode > 3 || dim < 2 || dim > 3 || n < 1 || n > 16) return LaunchShape{0, 0};
+  if (mode < 0 || mode >= kNumModes || dim < 2 || dim > 3 || n < 1 || n > 16) return LaunchShape{0, 0};
   const int v = g_shape[mode][dim - 2][n].load(std::memory_order_relaxed);
   if (v < 0) return default_shape(mode, dim, n);
   return LaunchShape{v >> 4, v & 15};
@@ -72,7 +76,7 @@ LaunchShape launch_shape(int mode, int dim, int n) {
 
 int set_launch_shape(int mode, int dim, int n, int blocks_per_cu, int variant) {
   init_shapes();
-  if (mode < 0 || mode > 3) return -1;
+  if (mode < 0 || mode >= kNumModes) return -1;
   if (dim < 2 || dim > 3) return -2;
   if (n < 1 || n > 16) return -3;
   if (blocks_per_cu < -1 || blocks_per_cu > 64) return -4;
@@ -92,6 +96,10 @@ int fwd3d_f64(int n, const double* A, const double* B, const double* C, const do
 int fwd3d_bf16x3(int n, const float* A, const float* B, const float* C, const float* X, float* Y, int64_t batch,
                  hipStream_t s) {
   return n <= 8 ? fwd3d_bf16x3_lo(n, A, B, C, X, Y, batch, s) : fwd3d_bf16x3_hi(n, A, B, C, X, Y, batch, s);
+}
+int fwd3d_bf16x6(int n, const float* A, const float* B, const float* C, const float* X, float* Y, int64_t batch,
+                 hipStream_t s) {
+  return n <= 8 ? fwd3d_bf16x6_lo(n, A, B, C, X, Y, batch, s) : fwd3d_bf16x6_hi(n, A, B, C, X, Y, batch, s);
 }
 int fwd3d_bf16(int n, const uint16_t* A, const uint16_t* B, const uint16_t* C, const uint16_t* X, uint16_t* Y,
                int64_t batch, hipStream_t s) {
@@ -210,6 +218,27 @@ int check_backward(int dim, int n, const T* X, const T* dY, const T* dX, const v
 
 }  // namespace
 
+namespace {
+
+// Shared body of the 3-D FP32 extended entry points: checks, factor
+// preparation into ws, then the plain kernels (beta == 0) or the beta kernel
+// on the prepared factors, all on `stream`.
+int ex3d_f32_call(int n, char opA, char opB, char opC, float alpha, const float* A, const float* B, const float* C,
+                  const float* X, float beta, float* Y, int64_t batch, void* ws, size_t ws_bytes,
+                  hipStream_t stream) {
+  const char ops[3] = {opA, opB, opC};
+  const float* mats[3] = {A, B, C};
+  bool skip, transx;
+  if (int rc = prepare_ex<float>(3, n, ops, alpha, mats, X, Y, batch, ws, ws_bytes, stream, &skip, &transx))
+    return rc;
+  if (skip) return 0;
+  const float* P = static_cast<const float*>(ws);
+  return finish_launch(beta != 0.0f ? kron::ex3d_f32(n, P, P + n * n, P + 2 * n * n, X, Y, batch, beta, stream)
+                                     : kron::fwd3d_f32(n, P, P + n * n, P + 2 * n * n, X, Y, batch, stream, false));
+}
+
+}  // namespace
+
 extern "C" {
 
 int kron2d_batched_f32(int n, const float* A, const float* B, const float* X, float* Y, int64_t batch,
@@ -252,6 +281,20 @@ int kron3d_batched_f32_bf16x3(int n, const float* A, const float* B, const float
   if (int rc = check3d(n, A, B, C, X, Y, batch)) return rc;
   if (batch == 0) return 0;
   return finish_launch(kron::fwd3d_bf16x3(n, A, B, C, X, Y, batch, stream));
+}
+
+int kron2d_batched_f32_bf16x6(int n, const float* A, const float* B, const float* X, float* Y, int64_t batch,
+                              hipStream_t stream) {
+  if (int rc = check2d(n, A, B, X, Y, batch)) return rc;
+  if (batch == 0) return 0;
+  return finish_launch(kron::fwd2d_bf16x6(n, A, B, X, Y, batch, stream));
+}
+
+int kron3d_batched_f32_bf16x6(int n, const float* A, const float* B, const float* C, const float* X, float* Y,
+                              int64_t batch, hipStream_t stream) {
+  if (int rc = check3d(n, A, B, C, X, Y, batch)) return rc;
+  if (batch == 0) return 0;
+  return finish_launch(kron::fwd3d_bf16x6(n, A, B, C, X, Y, batch, stream));
 }
 
 int kron2d_batched_bf16(int n, const uint16_t* A, const uint16_t* B, const uint16_t* X, uint16_t* Y,
@@ -361,6 +404,84 @@ int kron3d_backward_f64(int n, const double* A, const double* B, const double* C
   return 0;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Validity of one backward group descriptor (before anything is launched).
+bool grad_group_ok(const kron_group_grad_t& d) {
+  if ((d.dim != 2 && d.dim != 3) || d.n < 1 || d.n > KRON_MAX_N || d.count < 0) return false;
+  if (d.mode != KRON_MODE_F32 && d.mode != KRON_MODE_F64) return false;
+  if (d.count == 0) return true;
+  if (!d.A || !d.B || (d.dim == 3 && !d.C) || !d.dY) return false;
+  const bool factors = d.dA || d.dB || (d.dim == 3 && d.dC);
+  if (factors && !d.X) return false;
+  if (d.dX && (d.dX == d.dY || d.dX == d.X)) return false;
+  return true;
+}
+
+// Workspace slice of one group: its backward workspace, 256-byte aligned.
+size_t grad_group_bytes(const kron_group_grad_t& d) {
+  const size_t b = kron_backward_workspace_size(d.dim, d.n, d.count, d.mode);
+  return (b + 255) / 256 * 256;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t kron_grouped_backward_workspace_size(const kron_group_grad_t* groups, int ngroups) {
+  if (!groups || ngroups < 1) return 0;
+  size_t total = 0;
+  for (int i = 0; i < ngroups; ++i) {
+    if (!grad_group_ok(groups[i])) return 0;
+    total += grad_group_bytes(groups[i]);
+  }
+  return total;
+}
+
+int kron_grouped_backward(const kron_group_grad_t* groups, int ngroups, void* ws, size_t ws_bytes,
+                          hipStream_t stream) {
+  if (!groups) return -1;
+  if (ngroups < 1) return -2;
+  size_t need = 0;
+  for (int i = 0; i < ngroups; ++i) {
+    if (!grad_group_ok(groups[i])) return -1;
+    need += grad_group_bytes(groups[i]);
+  }
+  if (need > 0 && !ws) return -3;
+  if (ws_bytes < need) return -4;
+  uint8_t* at = static_cast<uint8_t*>(ws);
+  for (int i = 0; i < ngroups; ++i) {
+    const kron_group_grad_t& d = groups[i];
+    const size_t b = grad_group_bytes(d);
+    void* w = b ? at : nullptr;
+    int rc = 0;
+    if (d.mode == KRON_MODE_F32) {
+      using T = float;
+      if (d.dim == 2)
+        rc = kron2d_backward_f32(d.n, (const T*)d.A, (const T*)d.B, (const T*)d.X, (const T*)d.dY, (T*)d.dX,
+                                 (T*)d.dA, (T*)d.dB, d.count, w, b, stream);
+      else
+        rc = kron3d_backward_f32(d.n, (const T*)d.A, (const T*)d.B, (const T*)d.C, (const T*)d.X, (const T*)d.dY,
+                                 (T*)d.dX, (T*)d.dA, (T*)d.dB, (T*)d.dC, d.count, w, b, stream);
+    } else {
+      using T = double;
+      if (d.dim == 2)
+        rc = kron2d_backward_f64(d.n, (const T*)d.A, (const T*)d.B, (const T*)d.X, (const T*)d.dY, (T*)d.dX,
+                                 (T*)d.dA, (T*)d.dB, d.count, w, b, stream);
+      else
+        rc = kron3d_backward_f64(d.n, (const T*)d.A, (const T*)d.B, (const T*)d.C, (const T*)d.X, (const T*)d.dY,
+                                 (T*)d.dX, (T*)d.dA, (T*)d.dB, (T*)d.dC, d.count, w, b, stream);
+    }
+    // descriptors were checked above, so only a launch failure can end the loop
+    if (rc > 0) return rc;
+    if (rc < 0) return -1;
+    at += b;
+  }
+  return 0;
+}
+
 size_t kron_grouped_workspace_size(const kron_group_t* groups, int ngroups) {
   return kron::grouped_workspace_bytes(groups, ngroups);
 }
@@ -453,15 +574,7 @@ int kron2d_batched_ex_f64(int n, char opA, char opB, char opX, double alpha, con
 int kron3d_batched_ex_f32(int n, char opA, char opB, char opC, float alpha, const float* A, const float* B,
                           const float* C, const float* X, float beta, float* Y, int64_t batch, void* ws,
                           size_t ws_bytes, hipStream_t stream) {
-  const char ops[3] = {opA, opB, opC};
-  const float* mats[3] = {A, B, C};
-  bool skip, transx;
-  if (int rc = prepare_ex<float>(3, n, ops, alpha, mats, X, Y, batch, ws, ws_bytes, stream, &skip, &transx))
-    return rc;
-  if (skip) return 0;
-  const float* P = static_cast<const float*>(ws);
-  return finish_launch(beta != 0.0f ? kron::ex3d_f32(n, P, P + n * n, P + 2 * n * n, X, Y, batch, beta, stream)
-                                     : kron::fwd3d_f32(n, P, P + n * n, P + 2 * n * n, X, Y, batch, stream, false));
+  return ex3d_f32_call(n, opA, opB, opC, alpha, A, B, C, X, beta, Y, batch, ws, ws_bytes, stream);
 }
 
 int kron3d_batched_ex_f64(int n, char opA, char opB, char opC, double alpha, const double* A, const double* B,
@@ -501,7 +614,7 @@ int kron_set_launch(int mode, int dim, int n, int blocks_per_cu, int variant) {
 int kron_autotune(int mode, int dim, int n, const void* A, const void* B, const void* C, const void* X, void* Y,
                   int64_t batch, int reps, hipStream_t stream, int* best_blocks, int* best_variant,
                   float* best_ms) {
-  if (mode < 0 || mode > 3) return -1;
+  if (mode < 0 || mode >= kron::kNumModesAbi) return -1;
   if (dim < 2 || dim > 3) return -2;
   if (n < 1 || n > KRON_MAX_N) return -3;
   if (!A) return -4;
@@ -519,6 +632,8 @@ int kron_autotune(int mode, int dim, int n, const void* A, const void* B, const 
       case 3: return kron3d_batched_f64(n, (const double*)A, (const double*)B, (const double*)C, (const double*)X, (double*)Y, batch, stream);
       case 4: return kron2d_batched_f32_bf16x3(n, (const float*)A, (const float*)B, (const float*)X, (float*)Y, batch, stream);
       case 5: return kron3d_batched_f32_bf16x3(n, (const float*)A, (const float*)B, (const float*)C, (const float*)X, (float*)Y, batch, stream);
+      case 8: return kron2d_batched_f32_bf16x6(n, (const float*)A, (const float*)B, (const float*)X, (float*)Y, batch, stream);
+      case 9: return kron3d_batched_f32_bf16x6(n, (const float*)A, (const float*)B, (const float*)C, (const float*)X, (float*)Y, batch, stream);
       case 6: return kron2d_batched_bf16(n, (const uint16_t*)A, (const uint16_t*)B, (const uint16_t*)X, (uint16_t*)Y, batch, stream);
       default: return kron3d_batched_bf16(n, (const uint16_t*)A, (const uint16_t*)B, (const uint16_t*)C, (const uint16_t*)X, (uint16_t*)Y, batch, stream);
     }
@@ -569,7 +684,7 @@ int kron_autotune(int mode, int dim, int n, const void* A, const void* B, const 
 }
 
 int kron_get_launch(int mode, int dim, int n, int* blocks_per_cu, int* variant) {
-  if (mode < 0 || mode > 3) return -1;
+  if (mode < 0 || mode >= kron::kNumModesAbi) return -1;
   if (dim < 2 || dim > 3) return -2;
   if (n < 1 || n > 16) return -3;
   if (!blocks_per_cu) return -4;

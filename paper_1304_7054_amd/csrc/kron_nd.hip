@@ -1,0 +1,588 @@
+// The general batched action: d-dimensional operands for any d >= 1
+// (Section 2.1 generalises the summation to n-D arrays), rectangular factors
+// op(F_k) of size m_k x n_k with op in {N, T, C} and complex entries (Section
+// 2.2), alpha and beta, and factors that may change along the batch (the
+// case Section 6 names).  Real FP32 / FP64 and complex (C: FP32 pairs, Z:
+// FP64 pairs).
+//
+// The action is d mode products, fastest index first, each one pass over
+// HBM through the caller's workspace (ping-pong arrays), the way the paper
+// builds its 3-D kernel from a 2-D stage and a batched GEMM through a work
+// array (Section 4).  The fused 2-D / 3-D kernels keep every stage in
+// registers; this path instead covers any size and any d, and its one kernel
+// is the mode product
+//
+//     Out[u, i, v] = sum_a op(F)(i, a) * In[u, a, v],  u < pre, i < m, a < n, v < post
+//
+// on the 16x16x4 matrix cores: a tile is 16 output rows i by 16 "columns"
+// c = u * post + v, contracted in steps of four a.  When post > 1 the data
+// columns are the MFMA's B operand (lanes of a row group read 16 consecutive
+// v), when post == 1 (the fastest index) the data is the A operand (each lane
+// reads consecutive a of one u).  Complex products take four real MFMAs per
+// step: re += Fr xr - Fi xi, im += Fr xi + Fi xr.  With factors per operand
+// a tile's columns never straddle two operands.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kron.h"
+#include "kron_launch.hpp"
+
+namespace kron {
+namespace {
+
+constexpr int kNdMaxDim = 8;
+
+// Offset of column c of a pass: its digits, fastest first, each times its
+// stride (digit j = (c / prod_{i<j} mod_i) % mod_j; the last digit takes the
+// rest), plus `along` times the contracted (input) or produced (output)
+// index.  Dense intermediates have two digits (v < post, then u); the first
+// pass may read and the last pass may write strided storage (up to three
+// digits: the slower indices, then the operand).
+struct NdIndex {
+  int nlev;           // 1..3
+  int64_t mod[3];     // radix of digits 0 .. nlev - 2
+  int64_t stride[3];  // element stride of each digit
+  int64_t along;      // element stride of the contracted / produced index
+};
+
+__device__ __forceinline__ int64_t nd_offset(const NdIndex& ix, int64_t c) {
+  int64_t off = 0;
+  for (int j = 0; j < ix.nlev - 1; ++j) {
+    off += (c % ix.mod[j]) * ix.stride[j];
+    c /= ix.mod[j];
+  }
+  return off + c * ix.stride[ix.nlev - 1];
+}
+
+// One mode product.  Element counts and offsets are in elements (a complex
+// element is one unit; its two parts follow each other in memory).
+struct NdPass {
+  const void* X;
+  void* Y;
+  const void* F;
+  int64_t ldfp;   // factor stride between operands (0: shared)
+  int ld;         // leading dimension of the stored factor
+  int op;         // 0 N, 1 T, 2 C
+  int m, n;       // output / input extent of the contracted index
+  int conjx;      // conjugate the input elements (op(X) = X^* of the 2-D interface)
+  NdIndex in, out;
+  int64_t cols;   // columns per group (a group shares one factor)
+  int64_t chunks; // 16-column chunks per group
+  int rows;       // 16-row chunks of the output index
+};
+
+template <typename T>
+struct NdAcc;
+template <>
+struct NdAcc<float> {
+  using type = f32x4;
+  __device__ static f32x4 mma(float a, float b, f32x4 c) { return mfma_f32(a, b, c); }
+  __device__ static constexpr int drow(int g, int r) { return 4 * g + r; }
+};
+template <>
+struct NdAcc<double> {
+  using type = f64x4;
+  __device__ static f64x4 mma(double a, double b, f64x4 c) { return mfma_f64(a, b, c); }
+  __device__ static constexpr int drow(int g, int r) { return g + 4 * r; }
+};
+
+template <typename T, bool kC>
+__device__ __forceinline__ void ld_elem(const T* p, int64_t e, T& re, T& im) {
+  if constexpr (kC) {
+    re = __builtin_nontemporal_load(in_global(p) + 2 * e);
+    im = __builtin_nontemporal_load(in_global(p) + 2 * e + 1);
+  } else {
+    re = __builtin_nontemporal_load(in_global(p) + e);
+    im = T(0);
+  }
+}
+
+template <typename T, bool kC>
+__device__ __forceinline__ void st_elem(T* p, int64_t e, T re, T im) {
+  if constexpr (kC) {
+    __builtin_nontemporal_store(re, in_global(p) + 2 * e);
+    __builtin_nontemporal_store(im, in_global(p) + 2 * e + 1);
+  } else {
+    __builtin_nontemporal_store(re, in_global(p) + e);
+  }
+}
+
+// kDataA: the data is the MFMA's A operand (post == 1); otherwise B.
+// kBeta: Out <- alpha * product + beta * Out (the last pass); otherwise
+// Out <- alpha * product.
+template <typename T, bool kC, bool kDataA, bool kBeta>
+__global__ __launch_bounds__(kBlock) void kron_mode_kernel(NdPass P, int64_t ntiles, T ar, T ai, T br, T bi) {
+  using A = NdAcc<T>;
+  using acc_t = typename A::type;
+  const T* __restrict__ X = static_cast<const T*>(P.X);
+  T* __restrict__ Y = static_cast<T*>(P.Y);
+  const int l = threadIdx.x & 63, L = l & 15, g = l >> 4;
+  const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * kBlock) >> 6;
+  const int nk = (P.n + 15) / 16;
+  for (int64_t t = wave; t < ntiles; t += nwaves) {
+    const int ic = (int)(t % P.rows);
+    const int64_t ct = t / P.rows;
+    const int64_t grp = ct / P.chunks;
+    const int64_t cb = grp * P.cols + (ct % P.chunks) * 16;  // first column of the tile
+    const int64_t cend = (grp + 1) * P.cols;
+    const T* F = static_cast<const T*>(P.F) + grp * P.ldfp * (kC ? 2 : 1);
+    // The 16 columns of a tile usually share every digit but the fastest
+    // (cb's fastest digit + 15 stays below its radix): one offset for the
+    // tile plus the lane's step.  Otherwise every column is decomposed.
+    const bool fast_in = P.in.nlev == 1 || (cb % P.in.mod[0]) + 16 <= P.in.mod[0];
+    const bool fast_out = P.out.nlev == 1 || (cb % P.out.mod[0]) + 16 <= P.out.mod[0];
+    const int64_t in0 = nd_offset(P.in, cb), out0 = nd_offset(P.out, cb);
+    // the column this lane loads (both mappings: column cb + L)
+    const int64_t cl = cb + L;
+    const bool colok = cl < cend;
+    const int64_t xb = fast_in ? in0 + L * P.in.stride[0] : nd_offset(P.in, cl);
+    const int fi_row = 16 * ic + L;  // factor row held by this lane
+    acc_t dr = {0, 0, 0, 0}, di = {0, 0, 0, 0};
+    for (int kc = 0; kc < nk; ++kc) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int a = 16 * kc + 4 * g + s;
+        T xr = 0, xi = 0, fr = 0, fi = 0;
+        if (colok && a < P.n) {
+          ld_elem<T, kC>(X, xb + (int64_t)a * P.in.along, xr, xi);
+          if (kC && P.conjx) xi = -xi;
+        }
+        if (fi_row < P.m && a < P.n) {
+          const int64_t e = P.op == 0 ? fi_row + (int64_t)P.ld * a : a + (int64_t)P.ld * fi_row;
+          if constexpr (kC) {
+            fr = in_global(F)[2 * e];
+            fi = in_global(F)[2 * e + 1];
+            if (P.op == 2) fi = -fi;
+          } else {
+            fr = in_global(F)[e];
+          }
+        }
+        if constexpr (kDataA) {
+          dr = A::mma(xr, fr, dr);
+          if constexpr (kC) {
+            dr = A::mma(xi, -fi, dr);
+            di = A::mma(xi, fr, di);
+            di = A::mma(xr, fi, di);
+          }
+        } else {
+          dr = A::mma(fr, xr, dr);
+          if constexpr (kC) {
+            dr = A::mma(-fi, xi, dr);
+            di = A::mma(fr, xi, di);
+            di = A::mma(fi, xr, di);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = kDataA ? 16 * ic + L : 16 * ic + A::drow(g, r);
+      const int j = kDataA ? A::drow(g, r) : L;  // column of the tile
+      if (i >= P.m || cb + j >= cend) continue;
+      const int64_t e = (fast_out ? out0 + j * P.out.stride[0] : nd_offset(P.out, cb + j)) + (int64_t)i * P.out.along;
+      T yr = ar * dr[r] - ai * di[r];
+      T yi = ar * di[r] + ai * dr[r];
+      if constexpr (kBeta) {
+        T or_, oi;
+        ld_elem<T, kC>(Y, e, or_, oi);
+        yr = yr + (br * or_ - bi * oi);
+        yi = yi + (br * oi + bi * or_);
+      }
+      st_elem<T, kC>(Y, e, yr, yi);
+    }
+  }
+}
+
+template <typename T, bool kC, bool kDataA, bool kBeta>
+void launch_mode(const NdPass& P, int64_t ntiles, T ar, T ai, T br, T bi, hipStream_t stream) {
+  auto k = kron_mode_kernel<T, kC, kDataA, kBeta>;
+  hipLaunchKernelGGL(k, dim3(grid_blocks(ntiles, occupancy_blocks(k), 0)), dim3(kBlock), 0, stream, P, ntiles, ar, ai,
+                     br, bi);
+}
+
+template <typename T, bool kC>
+void run_pass(const NdPass& P, int64_t ntiles, bool data_a, bool beta, T ar, T ai, T br, T bi, hipStream_t s) {
+  if (data_a) {
+    if (beta) launch_mode<T, kC, true, true>(P, ntiles, ar, ai, br, bi, s);
+    else launch_mode<T, kC, true, false>(P, ntiles, ar, ai, br, bi, s);
+  } else {
+    if (beta) launch_mode<T, kC, false, true>(P, ntiles, ar, ai, br, bi, s);
+    else launch_mode<T, kC, false, false>(P, ntiles, ar, ai, br, bi, s);
+  }
+}
+
+int op_code(char c) {
+  switch (c) {
+    case 'N': case 'n': return 0;
+    case 'T': case 't': return 1;
+    case 'C': case 'c': return 2;
+    default: return -1;
+  }
+}
+
+// Elements after pass k (k = d..0: d is the input, 0 the output): extents
+// n_0 .. n_{k-1}, m_k .. m_{d-1}.
+int64_t extent_after(int d, const int* m, const int* n, int k) {
+  int64_t s = 1;
+  for (int j = 0; j < d; ++j) s *= j < k ? n[j] : m[j];
+  return s;
+}
+
+// Scalars of one intermediate array (the largest one), 0 when d == 1.
+int64_t nd_inter_elems(int d, const int* m, const int* n, int64_t batch) {
+  int64_t big = 0;
+  for (int k = 1; k < d; ++k) {
+    const int64_t e = extent_after(d, m, n, k) * batch;
+    if (e > big) big = e;
+  }
+  return big;
+}
+
+size_t nd_ws_bytes(int d, const int* m, const int* n, int64_t batch, size_t elem) {
+  const int64_t inter = nd_inter_elems(d, m, n, batch);
+  const int copies = d >= 3 ? 2 : (d == 2 ? 1 : 0);
+  const size_t one = ((size_t)inter * elem + 255) / 256 * 256;
+  return one * (size_t)copies;
+}
+
+bool sizes_ok(int d, const int* m, const int* n) {
+  if (d < 1 || d > kNdMaxDim || !m || !n) return false;
+  double ex = 1, ey = 1;
+  for (int k = 0; k < d; ++k) {
+    if (m[k] < 1 || n[k] < 1 || m[k] > KRON_ND_MAX_EXTENT || n[k] > KRON_ND_MAX_EXTENT) return false;
+    ex *= n[k];
+    ey *= m[k];
+  }
+  return ex < 9e15 && ey < 9e15;
+}
+
+// Strided operand storage of the first pass's input or the last pass's
+// output (d <= 3): element stride of each index and between operands.
+struct NdStrides {
+  int64_t s[3];
+  int64_t sp;
+};
+
+// Index of a dense pass: In[u, a, v] / Out[u, i, v] with v < post and
+// extent e of the middle index.
+NdIndex dense_index(int64_t e, int64_t post) {
+  NdIndex ix{};
+  if (post == 1) {
+    ix.nlev = 1;
+    ix.stride[0] = e;
+    ix.along = 1;
+  } else {
+    ix.nlev = 2;
+    ix.mod[0] = post;
+    ix.stride[0] = 1;
+    ix.stride[1] = e * post;
+    ix.along = post;
+  }
+  return ix;
+}
+
+// Index of strided storage with extents ext[0..d-1] when index k0 is the
+// contracted one (the fastest, d - 1, for the first pass) or the produced
+// one (the slowest, 0, for the last pass): the other indices are the
+// digits, fastest first, then the operand.
+NdIndex strided_index(int d, const int* ext, const NdStrides& st, int k0) {
+  NdIndex ix{};
+  int lev = 0;
+  for (int j = d - 1; j >= 0; --j) {
+    if (j == k0) continue;
+    ix.mod[lev] = ext[j];
+    ix.stride[lev] = st.s[j];
+    ++lev;
+  }
+  ix.stride[lev] = st.sp;
+  ix.nlev = lev + 1;
+  ix.along = st.s[k0];
+  return ix;
+}
+
+// Argument positions of kron_nd_batched_*: d 1, m 2, n 3, ops 4, alpha 5,
+// factors 6, ldf 7, ldfp 8, X 9, beta 10, Y 11, batch 12, ws 13, ws_bytes 14.
+// xs / ys: strided storage of X and Y (d <= 3), or nullptr for packed
+// operands; conjx conjugates X on the way in.  The caller checks them.
+template <typename T, bool kC>
+int nd_run(int d, const int* m, const int* n, const char* ops, T ar, T ai, const T* const* F, const int* ldf,
+           const int64_t* ldfp, const T* X, T br, T bi, T* Y, int64_t batch, void* ws, size_t ws_bytes,
+           hipStream_t stream, const NdStrides* xs = nullptr, const NdStrides* ys = nullptr, bool conjx = false) {
+  if (d < 1 || d > kNdMaxDim) return -1;
+  if (!m || !sizes_ok(d, m, n)) return -2;
+  if (!n) return -3;
+  if (!ops) return -4;
+  int opc[kNdMaxDim];
+  for (int k = 0; k < d; ++k)
+    if ((opc[k] = op_code(ops[k])) < 0) return -4;  // 'C' on real data is 'T'
+  if (!F) return -6;
+  for (int k = 0; k < d; ++k)
+    if (!F[k]) return -6;
+  if (!ldf) return -7;
+  for (int k = 0; k < d; ++k)
+    if (ldf[k] < (opc[k] == 0 ? m[k] : n[k])) return -7;
+  if (!ldfp) return -8;
+  for (int k = 0; k < d; ++k)
+    if (ldfp[k] < 0) return -8;
+  if (!X) return -9;
+  if (!Y || (const void*)Y == (const void*)X) return -11;
+  if (batch < 0) return -12;
+  if (batch == 0) return 0;
+  const size_t elem = sizeof(T) * (kC ? 2 : 1);
+  const size_t need = nd_ws_bytes(d, m, n, batch, elem);
+  if (need > 0 && (!ws || reinterpret_cast<uintptr_t>(ws) % 16 != 0)) return -13;
+  if (ws_bytes < need) return -14;
+  const size_t half = d >= 3 ? need / 2 : need;
+  T* buf[2] = {static_cast<T*>(ws), reinterpret_cast<T*>(static_cast<uint8_t*>(ws) + half)};
+  const bool has_beta = br != T(0) || bi != T(0);
+  const void* in = X;
+  int which = 0;
+  for (int k = d - 1; k >= 0; --k) {
+    NdPass P;
+    P.X = in;
+    P.Y = k == 0 ? static_cast<void*>(Y) : static_cast<void*>(buf[which]);
+    P.F = F[k];
+    P.ldfp = ldfp[k];
+    P.ld = ldf[k];
+    P.op = opc[k];
+    P.m = m[k];
+    P.n = n[k];
+    P.conjx = conjx && k == d - 1;
+    int64_t pre = 1, post = 1;
+    for (int j = 0; j < k; ++j) pre *= n[j];
+    for (int j = k + 1; j < d; ++j) post *= m[j];
+    P.in = (k == d - 1 && xs) ? strided_index(d, n, *xs, d - 1) : dense_index(n[k], post);
+    if (k == 0 && ys) {
+      P.out = strided_index(d, m, *ys, 0);
+    } else {
+      P.out = dense_index(m[k], post);
+    }
+    const bool shared = ldfp[k] == 0;
+    P.cols = shared ? batch * pre * post : pre * post;
+    const int64_t groups = shared ? 1 : batch;
+    P.chunks = (P.cols + 15) / 16;
+    P.rows = (m[k] + 15) / 16;
+    const int64_t ntiles = groups * P.chunks * P.rows;
+    const bool last = k == 0;
+    run_pass<T, kC>(P, ntiles, post == 1, last && has_beta, last ? ar : T(1), last ? ai : T(0), br, bi, stream);
+    in = P.Y;
+    which ^= 1;
+  }
+  return 0;
+}
+
+// Checks shared by the TKRON-style entry points (Section 3's argument lists
+// with rectangular factors): returns 0 or -position.
+int rect_op(char c) { return op_code(c); }
+bool extent_ok(int v) { return v >= 1 && v <= KRON_ND_MAX_EXTENT; }
+
+// Workspace check at the caller's argument positions (kws: ws, kws + 1: ws_bytes).
+int rect_ws_check(int d, const int* m, const int* n, int64_t batch, size_t elem, const void* ws, size_t ws_bytes,
+                  int kws) {
+  if (batch <= 0) return 0;
+  const size_t need = nd_ws_bytes(d, m, n, batch, elem);
+  if (need > 0 && (!ws || reinterpret_cast<uintptr_t>(ws) % 16 != 0)) return -kws;
+  if (ws_bytes < need) return -(kws + 1);
+  return 0;
+}
+
+template <typename T, bool kC>
+int rect_run(int d, const char* ops, const int* m, const int* nn, int64_t batch, T ar, T ai, const T* const* F,
+             const int* ld, const T* X, const NdStrides& xs, T br, T bi, T* Y, const NdStrides& ys, bool conjx,
+             void* ws, size_t ws_bytes, hipStream_t stream) {
+  int64_t ldfp[3] = {0, 0, 0};
+  const int rc = nd_run<T, kC>(d, m, nn, ops, ar, ai, F, ld, ldfp, X, br, bi, Y, batch, ws, ws_bytes, stream, &xs,
+                               &ys, conjx);
+  if (rc != 0) return rc;
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? 0 : (int)e;
+}
+
+}  // namespace
+}  // namespace kron
+
+extern "C" {
+
+size_t kron_nd_workspace_size(int d, const int* m, const int* n, int64_t batch, int type) {
+  if (!kron::sizes_ok(d, m, n) || batch < 0) return 0;
+  size_t elem;
+  switch (type) {
+    case KRON_MODE_F32: elem = 4; break;
+    case KRON_MODE_F64: elem = 8; break;
+    case KRON_TYPE_C32: elem = 8; break;
+    case KRON_TYPE_C64: elem = 16; break;
+    default: return 0;
+  }
+  return kron::nd_ws_bytes(d, m, n, batch, elem);
+}
+
+int kron_nd_batched_f32(int d, const int* m, const int* n, const char* ops, float alpha, const float* const* factors,
+                        const int* ldf, const int64_t* ldfp, const float* X, float beta, float* Y, int64_t batch,
+                        void* ws, size_t ws_bytes, hipStream_t stream) {
+  int rc = kron::nd_run<float, false>(d, m, n, ops, alpha, 0.f, factors, ldf, ldfp, X, beta, 0.f, Y, batch, ws,
+                                      ws_bytes, stream);
+  if (rc != 0) return rc;
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? 0 : (int)e;
+}
+
+int kron_nd_batched_f64(int d, const int* m, const int* n, const char* ops, double alpha,
+                        const double* const* factors, const int* ldf, const int64_t* ldfp, const double* X,
+                        double beta, double* Y, int64_t batch, void* ws, size_t ws_bytes, hipStream_t stream) {
+  int rc = kron::nd_run<double, false>(d, m, n, ops, alpha, 0.0, factors, ldf, ldfp, X, beta, 0.0, Y, batch, ws,
+                                       ws_bytes, stream);
+  if (rc != 0) return rc;
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? 0 : (int)e;
+}
+
+int kron_nd_batched_c32(int d, const int* m, const int* n, const char* ops, kron_c32_t alpha,
+                        const kron_c32_t* const* factors, const int* ldf, const int64_t* ldfp, const kron_c32_t* X,
+                        kron_c32_t beta, kron_c32_t* Y, int64_t batch, void* ws, size_t ws_bytes,
+                        hipStream_t stream) {
+  int rc = kron::nd_run<float, true>(d, m, n, ops, alpha.re, alpha.im,
+                                     reinterpret_cast<const float* const*>(factors), ldf, ldfp,
+                                     reinterpret_cast<const float*>(X), beta.re, beta.im,
+                                     reinterpret_cast<float*>(Y), batch, ws, ws_bytes, stream);
+  if (rc != 0) return rc;
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? 0 : (int)e;
+}
+
+int kron_nd_batched_c64(int d, const int* m, const int* n, const char* ops, kron_c64_t alpha,
+                        const kron_c64_t* const* factors, const int* ldf, const int64_t* ldfp, const kron_c64_t* X,
+                        kron_c64_t beta, kron_c64_t* Y, int64_t batch, void* ws, size_t ws_bytes,
+                        hipStream_t stream) {
+  int rc = kron::nd_run<double, true>(d, m, n, ops, alpha.re, alpha.im,
+                                      reinterpret_cast<const double* const*>(factors), ldf, ldfp,
+                                      reinterpret_cast<const double*>(X), beta.re, beta.im,
+                                      reinterpret_cast<double*>(Y), batch, ws, ws_bytes, stream);
+  if (rc != 0) return rc;
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? 0 : (int)e;
+}
+
+}  // extern "C"
+
+// ---- TKRON1 / TKRON2 / TKRON3 with rectangular factors (Section 3) ---------
+
+#define KRON_RECT_TYPES(F) \
+  F(f32, float, float, false, a, 0.f, b, 0.f) \
+  F(f64, double, double, false, a, 0.0, b, 0.0) \
+  F(c32, float, kron_c32_t, true, a.re, a.im, b.re, b.im) \
+  F(c64, double, kron_c64_t, true, a.re, a.im, b.re, b.im)
+
+// 1-D: positions opA 1, ma 2, na 3, batch 4, alpha 5, A 6, lda 7, X 8,
+// ldxp 9, beta 10, Y 11, ldyp 12, ws 13, ws_bytes 14.
+#define KRON_RECT1(TAG, R, E, CPLX, AR, AI, BR, BI)                                                              \
+  int kron1d_batched_rect_##TAG(char opA, int ma, int na, int64_t batch, E a, const E* A, int lda, const E* X,  \
+                                int64_t ldxp, E b, E* Y, int64_t ldyp, void* ws, size_t ws_bytes,               \
+                                hipStream_t stream) {                                                           \
+    if (kron::rect_op(opA) < 0) return -1;                                                                      \
+    if (!kron::extent_ok(ma)) return -2;                                                                        \
+    if (!kron::extent_ok(na)) return -3;                                                                        \
+    if (batch < 0) return -4;                                                                                   \
+    if (!A) return -6;                                                                                          \
+    if (lda < (kron::rect_op(opA) == 0 ? ma : na)) return -7;                                                   \
+    if (!X) return -8;                                                                                          \
+    if (ldxp < 0) return -9;                                                                                    \
+    if (!Y || (const void*)Y == (const void*)X) return -11;                                                     \
+    if (ldyp < ma) return -12;                                                                                  \
+    const int m[1] = {ma}, n[1] = {na}, ld[1] = {lda};                                                          \
+    const char ops[1] = {opA};                                                                                  \
+    const R* F[1] = {reinterpret_cast<const R*>(A)};                                                            \
+    const kron::NdStrides xs{{1, 0, 0}, ldxp}, ys{{1, 0, 0}, ldyp};                                              \
+    return kron::rect_run<R, CPLX>(1, ops, m, n, batch, AR, AI, F, ld, reinterpret_cast<const R*>(X), xs, BR,   \
+                                   BI, reinterpret_cast<R*>(Y), ys, false, ws, ws_bytes, stream);               \
+  }
+
+// 2-D: positions opA 1, opB 2, opX 3, ma 4, na 5, mb 6, nb 7, batch 8,
+// alpha 9, A 10, lda 11, B 12, ldb 13, X 14, ldx 15, ldxp 16, beta 17,
+// Y 18, ldy 19, ldyp 20, ws 21, ws_bytes 22.
+#define KRON_RECT2(TAG, R, E, CPLX, AR, AI, BR, BI)                                                              \
+  int kron2d_batched_rect_##TAG(char opA, char opB, char opX, int ma, int na, int mb, int nb, int64_t batch,    \
+                                E a, const E* A, int lda, const E* B, int ldb, const E* X, int64_t ldx,         \
+                                int64_t ldxp, E b, E* Y, int64_t ldy, int64_t ldyp, void* ws, size_t ws_bytes,  \
+                                hipStream_t stream) {                                                           \
+    const int oa = kron::rect_op(opA), ob = kron::rect_op(opB), ox = kron::rect_op(opX);                        \
+    if (oa < 0) return -1;                                                                                      \
+    if (ob < 0) return -2;                                                                                      \
+    if (ox < 0) return -3;                                                                                      \
+    if (!kron::extent_ok(ma)) return -4;                                                                        \
+    if (!kron::extent_ok(na)) return -5;                                                                        \
+    if (!kron::extent_ok(mb)) return -6;                                                                        \
+    if (!kron::extent_ok(nb)) return -7;                                                                        \
+    if (batch < 0) return -8;                                                                                   \
+    if (!A) return -10;                                                                                         \
+    if (lda < (oa == 0 ? ma : na)) return -11;                                                                  \
+    if (!B) return -12;                                                                                         \
+    if (ldb < (ob == 0 ? mb : nb)) return -13;                                                                  \
+    if (!X) return -14;                                                                                         \
+    if (ldx < 0) return -15;                                                                                    \
+    if (ldxp < 0) return -16;                                                                                   \
+    if (!Y || (const void*)Y == (const void*)X) return -18;                                                     \
+    if (ldy < mb) return -19;                                                                                   \
+    if (ldyp < ldy * ma) return -20;                                                                            \
+    const int m[2] = {ma, mb}, n[2] = {na, nb}, ld[2] = {lda, ldb};                                             \
+    if (int rc = kron::rect_ws_check(2, m, n, batch, sizeof(E), ws, ws_bytes, 21)) return rc;                  \
+    const char ops[2] = {opA, opB};                                                                             \
+    const R* F[2] = {reinterpret_cast<const R*>(A), reinterpret_cast<const R*>(B)};                             \
+    /* op(X_p)(a0, a1), a1 the fast index: X_p(a1, a0) at a1 + ldx a0, or (op T / C) X_p(a0, a1) at */          \
+    /* a0 + ldx a1 */                                                                                           \
+    const kron::NdStrides xs = ox == 0 ? kron::NdStrides{{ldx, 1, 0}, ldxp} : kron::NdStrides{{1, ldx, 0}, ldxp}; \
+    const kron::NdStrides ys{{ldy, 1, 0}, ldyp};                                                                \
+    return kron::rect_run<R, CPLX>(2, ops, m, n, batch, AR, AI, F, ld, reinterpret_cast<const R*>(X), xs, BR,   \
+                                   BI, reinterpret_cast<R*>(Y), ys, ox == 2, ws, ws_bytes, stream);             \
+  }
+
+// 3-D: positions opA 1, opB 2, opC 3, ma 4, na 5, mb 6, nb 7, mc 8, nc 9,
+// batch 10, alpha 11, A 12, lda 13, B 14, ldb 15, C 16, ldc 17, X 18,
+// ldx 19, ldx2 20, ldxp 21, beta 22, Y 23, ldy 24, ldy2 25, ldyp 26, ws 27,
+// ws_bytes 28.
+#define KRON_RECT3(TAG, R, E, CPLX, AR, AI, BR, BI)                                                              \
+  int kron3d_batched_rect_##TAG(char opA, char opB, char opC, int ma, int na, int mb, int nb, int mc, int nc,   \
+                                int64_t batch, E a, const E* A, int lda, const E* B, int ldb, const E* C,       \
+                                int ldc, const E* X, int64_t ldx, int64_t ldx2, int64_t ldxp, E b, E* Y,        \
+                                int64_t ldy, int64_t ldy2, int64_t ldyp, void* ws, size_t ws_bytes,             \
+                                hipStream_t stream) {                                                           \
+    const int oa = kron::rect_op(opA), ob = kron::rect_op(opB), oc = kron::rect_op(opC);                        \
+    if (oa < 0) return -1;                                                                                      \
+    if (ob < 0) return -2;                                                                                      \
+    if (oc < 0) return -3;                                                                                      \
+    if (!kron::extent_ok(ma)) return -4;                                                                        \
+    if (!kron::extent_ok(na)) return -5;                                                                        \
+    if (!kron::extent_ok(mb)) return -6;                                                                        \
+    if (!kron::extent_ok(nb)) return -7;                                                                        \
+    if (!kron::extent_ok(mc)) return -8;                                                                        \
+    if (!kron::extent_ok(nc)) return -9;                                                                        \
+    if (batch < 0) return -10;                                                                                  \
+    if (!A) return -12;                                                                                         \
+    if (lda < (oa == 0 ? ma : na)) return -13;                                                                  \
+    if (!B) return -14;                                                                                         \
+    if (ldb < (ob == 0 ? mb : nb)) return -15;                                                                  \
+    if (!C) return -16;                                                                                         \
+    if (ldc < (oc == 0 ? mc : nc)) return -17;                                                                  \
+    if (!X) return -18;                                                                                         \
+    if (ldx < 0) return -19;                                                                                    \
+    if (ldx2 < 0) return -20;                                                                                   \
+    if (ldxp < 0) return -21;                                                                                   \
+    if (!Y || (const void*)Y == (const void*)X) return -23;                                                     \
+    if (ldy < mc) return -24;                                                                                   \
+    if (ldy2 < ldy * mb) return -25;                                                                            \
+    if (ldyp < ldy2 * ma) return -26;                                                                           \
+    const int m[3] = {ma, mb, mc}, n[3] = {na, nb, nc}, ld[3] = {lda, ldb, ldc};                                \
+    if (int rc = kron::rect_ws_check(3, m, n, batch, sizeof(E), ws, ws_bytes, 27)) return rc;                  \
+    const char ops[3] = {opA, opB, opC};                                                                        \
+    const R* F[3] = {reinterpret_cast<const R*>(A), reinterpret_cast<const R*>(B), reinterpret_cast<const R*>(C)}; \
+    const kron::NdStrides xs{{ldx2, ldx, 1}, ldxp}, ys{{ldy2, ldy, 1}, ldyp};                                   \
+    return kron::rect_run<R, CPLX>(3, ops, m, n, batch, AR, AI, F, ld, reinterpret_cast<const R*>(X), xs, BR,   \
+                                   BI, reinterpret_cast<R*>(Y), ys, false, ws, ws_bytes, stream);               \
+  }
+
+extern "C" {
+KRON_RECT_TYPES(KRON_RECT1)
+KRON_RECT_TYPES(KRON_RECT2)
+KRON_RECT_TYPES(KRON_RECT3)
+}  // extern "C"

@@ -36,6 +36,9 @@ int fwd3d_f64(int n, const double* A, const double* B, const double* C, const do
 int fwd2d_bf16x3(int n, const float* A, const float* B, const float* X, float* Y, int64_t batch, hipStream_t s);
 int fwd3d_bf16x3(int n, const float* A, const float* B, const float* C, const float* X, float* Y, int64_t batch,
                  hipStream_t s);
+int fwd2d_bf16x6(int n, const float* A, const float* B, const float* X, float* Y, int64_t batch, hipStream_t s);
+int fwd3d_bf16x6(int n, const float* A, const float* B, const float* C, const float* X, float* Y, int64_t batch,
+                 hipStream_t s);
 int fwd2d_bf16(int n, const uint16_t* A, const uint16_t* B, const uint16_t* X, uint16_t* Y, int64_t batch,
                hipStream_t s);
 int fwd3d_bf16(int n, const uint16_t* A, const uint16_t* B, const uint16_t* C, const uint16_t* X, uint16_t* Y,
@@ -53,6 +56,10 @@ int fwd3d_f64_hi(int n, const double* A, const double* B, const double* C, const
 int fwd3d_bf16x3_lo(int n, const float* A, const float* B, const float* C, const float* X, float* Y, int64_t batch,
                 hipStream_t s);
 int fwd3d_bf16x3_hi(int n, const float* A, const float* B, const float* C, const float* X, float* Y, int64_t batch,
+                hipStream_t s);
+int fwd3d_bf16x6_lo(int n, const float* A, const float* B, const float* C, const float* X, float* Y, int64_t batch,
+                hipStream_t s);
+int fwd3d_bf16x6_hi(int n, const float* A, const float* B, const float* C, const float* X, float* Y, int64_t batch,
                 hipStream_t s);
 int fwd3d_bf16_lo(int n, const uint16_t* A, const uint16_t* B, const uint16_t* C, const uint16_t* X, uint16_t* Y, int64_t batch,
                 hipStream_t s);

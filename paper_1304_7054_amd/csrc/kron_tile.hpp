@@ -292,6 +292,70 @@ struct ModeBF16x3 {
   __device__ static acc_t da_in(const fac_t& f, const acc_t& x) { return da(f, x); }
 };
 
+// bf16x6: every FP32 value v is split three ways, v = h + m + l with
+// h = bf16(v), m = bf16(v - h), l = bf16(v - h - m); both differences are
+// exact in FP32 and l takes the last bits exactly, so the three parts hold
+// all 24 significant bits.  A product v*w is taken as six bf16 products,
+// smallest first: h*wl + l*wh, then h*wm + m*wh, then h*wh + m*wm, each pair
+// one K=32 MFMA on packed data ([h | l] or [h | m]) chained through the
+// accumulator; the dropped terms (m*wl, l*wm, l*wl) are below 2^-23 of |v*w|.
+// Three MFMAs per step instead of bf16x3's two, for results as accurate as
+// plain FP32 on any data (bf16x3 keeps 16 significant bits per value).
+__device__ __forceinline__ void split3(const f32x4& x, bf16x4& h, bf16x4& m, bf16x4& l) {
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const __bf16 a = to_bf16(x[e]);
+    const float r1 = x[e] - from_bf16(a);
+    const __bf16 b = to_bf16(r1);
+    h[e] = a;
+    m[e] = b;
+    l[e] = to_bf16(r1 - from_bf16(b));
+  }
+}
+
+struct ModeBF16x6 {
+  using io_t = float;
+  using acc_t = f32x4;
+  struct fac_t {
+    bf16x8 lh;  // [wl | wh]: pairs with data [h | l]
+    bf16x8 mh;  // [wm | wh]: pairs with data [h | m]
+    bf16x8 hm;  // [wh | wm]: pairs with data [h | m]
+  };
+  static constexpr int kBytes = 4;
+  __device__ static constexpr int drow(int g, int r) { return 4 * g + r; }
+  template <int N, bool kTrans>
+  __device__ static fac_t load_fac(const io_t* M, int L, int g, int kmap) {
+    f32x4 v;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) v[s] = tile_entry<N, kTrans>(M, L, kmap == 0 ? 4 * g + s : drow(g, s));
+    bf16x4 h, m, l;
+    split3(v, h, m, l);
+    return fac_t{cat8(l, h), cat8(m, h), cat8(h, m)};
+  }
+  template <int kSteps = 4>
+  __device__ static acc_t da(const fac_t& f, const acc_t& x) {
+    bf16x4 h, m, l;
+    split3(x, h, m, l);
+    const bf16x8 dhl = cat8(h, l), dhm = cat8(h, m);
+    acc_t c = {0.f, 0.f, 0.f, 0.f};
+    c = mfma_bf16_k32(dhl, f.lh, c);
+    c = mfma_bf16_k32(dhm, f.mh, c);
+    return mfma_bf16_k32(dhm, f.hm, c);
+  }
+  template <int kSteps = 4>
+  __device__ static acc_t db(const fac_t& f, const acc_t& x) {
+    bf16x4 h, m, l;
+    split3(x, h, m, l);
+    const bf16x8 dhl = cat8(h, l), dhm = cat8(h, m);
+    acc_t c = {0.f, 0.f, 0.f, 0.f};
+    c = mfma_bf16_k32(f.lh, dhl, c);
+    c = mfma_bf16_k32(f.mh, dhm, c);
+    return mfma_bf16_k32(f.hm, dhm, c);
+  }
+  template <int kSteps = 4>
+  __device__ static acc_t da_in(const fac_t& f, const acc_t& x) { return da(f, x); }
+};
+
 // bf16 storage: the factors and the operands are exact bf16 values.  The
 // first stage multiplies bf16 by bf16 exactly (one K=16 MFMA); later stages
 // split the FP32 intermediate into hi + lo and take hi*m + lo*m in one K=32

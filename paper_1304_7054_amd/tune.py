@@ -14,7 +14,8 @@ import os
 
 from . import _binding as kb
 
-MODES = {"f32": kb.MODE_F32, "f64": kb.MODE_F64, "bf16x3": kb.MODE_BF16X3, "bf16": kb.MODE_BF16}
+MODES = {"f32": kb.MODE_F32, "f64": kb.MODE_F64, "bf16x3": kb.MODE_BF16X3, "bf16": kb.MODE_BF16,
+         "bf16x6": kb.MODE_BF16X6}
 
 
 def device_key():

@@ -15,6 +15,8 @@ FWD = {
     ("f64", 3): kron.kron3d_batched_f64,
     ("bf16x3", 2): kron.kron2d_batched_f32_bf16x3,
     ("bf16x3", 3): kron.kron3d_batched_f32_bf16x3,
+    ("bf16x6", 2): kron.kron2d_batched_f32_bf16x6,
+    ("bf16x6", 3): kron.kron3d_batched_f32_bf16x6,
     ("bf16", 2): kron.kron2d_batched_bf16,
     ("bf16", 3): kron.kron3d_batched_bf16,
     ("adj_f32", 2): kron.kron2d_batched_adjoint_f32,
@@ -23,7 +25,7 @@ FWD = {
     ("adj_f64", 3): kron.kron3d_batched_adjoint_f64,
 }
 
-IO_DTYPE = {"f32": np.float32, "bf16x3": np.float32, "adj_f32": np.float32,
+IO_DTYPE = {"f32": np.float32, "bf16x3": np.float32, "bf16x6": np.float32, "adj_f32": np.float32,
             "f64": np.float64, "adj_f64": np.float64}
 
 
@@ -76,7 +78,7 @@ def errors(got, want, batch):
     return float(norm), float(per.max()) if batch else 0.0
 
 
-TOL = {"f32": 1e-5, "adj_f32": 1e-5, "bf16x3": 1e-5, "f64": 1e-13, "adj_f64": 1e-13, "bf16": 1e-2}
+TOL = {"f32": 1e-5, "adj_f32": 1e-5, "bf16x3": 1e-5, "bf16x6": 1e-5, "f64": 1e-13, "adj_f64": 1e-13, "bf16": 1e-2}
 
 
 def tiles_batch(dim, n, tiles=3, extra=1):

@@ -35,14 +35,6 @@ FULL = [
 TOL = {"f32": 1e-5, "f64": 1e-13, "bf16x3": 1e-5, "bf16": 1e-2}
 
 
-def _log_uniform_(t, gen):
-    """In place: magnitudes exp(U[ln 1e-3, ln 1e3]) with a random sign (the
-    precision modes' value distribution)."""
-    mag = torch.empty_like(t, dtype=torch.float32).uniform_(np.log(1e-3), np.log(1e3), generator=gen).exp_()
-    sign = torch.empty_like(mag).bernoulli_(0.5, generator=gen).mul_(2).sub_(1)
-    t.copy_(mag * sign)
-
-
 @pytest.mark.parametrize("mode,dim,n,batch", FULL)
 def test_full_size_sampled(mode, dim, n, batch):
     _need_gpu()
@@ -50,7 +42,7 @@ def test_full_size_sampled(mode, dim, n, batch):
     if mode in ("bf16x3", "bf16"):
         gen = torch.Generator(device="cuda").manual_seed(workloads.SEED_BASE + 3)
         for t in mats + [X]:
-            _log_uniform_(t, gen)
+            workloads.log_uniform_device_(t, gen)
     Y.fill_(float("nan"))
     fn = bench.fn_for(mode, dim)
     assert fn(n, *mats, X, Y, batch) == 0

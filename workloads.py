@@ -63,6 +63,18 @@ def log_uniform(rng, size, dtype=np.float64, lo=1e-3, hi=1e3):
     return (sign * mag).astype(dtype)
 
 
+def log_uniform_device_(t, gen, lo=1e-3, hi=1e3):
+    """In place on a device tensor: the log_uniform distribution (magnitude
+    exp(U[ln lo, ln hi]), sign +-1 at probability 1/2) drawn with a seeded
+    torch generator; for the 1 GiB workloads, where host draws take long."""
+    import torch
+    mag = torch.empty(t.shape, dtype=torch.float32, device=t.device)
+    mag.uniform_(float(np.log(lo)), float(np.log(hi)), generator=gen).exp_()
+    sign = torch.empty_like(mag).bernoulli_(0.5, generator=gen).mul_(2).sub_(1)
+    t.copy_(mag * sign)
+    return t
+
+
 @dataclass
 class Problem:
     """One (dim, n) group of operands with its shared matrices."""
