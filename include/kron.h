@@ -347,6 +347,28 @@ int kron3d_batched_rect_c64(char opA, char opB, char opC, int ma, int na, int mb
                             int ldc, const kron_c64_t* X, int64_t ldx, int64_t ldx2, int64_t ldxp, kron_c64_t beta, kron_c64_t* Y,
                             int64_t ldy, int64_t ldy2, int64_t ldyp, void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* ---- allocation-free variant ------------------------------------------------------ */
+
+/* kron3d_batched_ex_f32 without a workspace argument, for callers that cannot
+   allocate device memory (code under HIP graph capture, tight serving loops,
+   harnesses that forbid allocation).  The prepared factors go to a device
+   array of the library (3 * 16 * 16 floats, 3 KiB: every n in 1..16 fits;
+   each GPU the library runs on holds its own copy until the process ends).
+   The call allocates nothing: no hipMalloc, hipFree or allocating library
+   routine.  Arguments, layout, results and status codes are those of
+   kron3d_batched_ex_f32 (an n beyond KRON_MAX_N, hence beyond the array,
+   returns -1); the device is the current one, as for every call.  On its
+   first call on a device the library looks up that device's array address
+   (a failure there is returned as a positive hipError_t).
+   Every call on one GPU shares that GPU's array, which keeps the last call's
+   prepared factors: calls that may overlap on one GPU (issued on different
+   streams without ordering between them, or from several host threads)
+   race and must be serialised by the caller.  Calls ordered on one stream
+   are safe. */
+int kron3d_batched_ex_f32_noalloc(int n, char opA, char opB, char opC, float alpha, const float* A,
+                                  const float* B, const float* C, const float* X, float beta, float* Y,
+                                  int64_t batch, hipStream_t stream);
+
 /* ---- Section 3's interface with leading dimensions ------------------------------ */
 
 /* The extended update above on strided storage, with the argument layout of

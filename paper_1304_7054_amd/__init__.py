@@ -21,6 +21,7 @@ from ._binding import (  # noqa: F401
     kron2d_batched_ex_f32,
     kron2d_batched_ex_f64,
     kron3d_batched_ex_f32,
+    kron3d_batched_ex_f32_noalloc,
     kron3d_batched_ex_f64,
     kron_ex_workspace_size,
     kron_nd_batched,

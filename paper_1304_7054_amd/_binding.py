@@ -83,6 +83,7 @@ SIGNATURES = {
     "kron2d_batched_ex_f64": "icccdpppdplpzS",
     "kron3d_batched_ex_f32": "icccfppppfplpzS",
     "kron3d_batched_ex_f64": "icccdppppdplpzS",
+    "kron3d_batched_ex_f32_noalloc": "icccfppppfplS",
     "kron1d_batched_f32": "icfpiplfpllpzS",
     "kron1d_batched_f64": "icdpipldpllpzS",
     "kron2d_batched_strided_f32": "icccfpipipllfplllpzS",
@@ -420,6 +421,25 @@ def kron3d_batched_ex_f32(n, opA, opB, opC, alpha, A, B, C, X, beta, Y, batch, w
 def kron3d_batched_ex_f64(n, opA, opB, opC, alpha, A, B, C, X, beta, Y, batch, ws=None, stream=None):
     return _ex_call("kron3d_batched_ex_f64", 3, torch.float64, MODE_F64, n, (opA, opB, opC), float(alpha),
                     (A, B, C), X, float(beta), Y, batch, ws, stream)
+
+
+def kron3d_batched_ex_f32_noalloc(n, opA, opB, opC, alpha, A, B, C, X, beta, Y, batch, stream=None):
+    """kron3d_batched_ex_f32 with no workspace: the library keeps the prepared
+    factors in its own device array (calls that overlap on one GPU race)."""
+    n, batch = int(n), int(batch)
+    if not 1 <= n <= 16:
+        raise ValueError(f"n must be in 1..16, got {n}")
+    if batch < 0:
+        raise ValueError("batch must be >= 0")
+    opc = [_op_char(op, f"op{i}") for i, op in enumerate((opA, opB, opC))]
+    ptrs = [_arr(M, torch.float32, n * n, f"factor {i}") for i, M in enumerate((A, B, C))]
+    size = batch * n ** 3
+    px = _arr(X, torch.float32, size, "X")
+    py = _arr(Y, torch.float32, size, "Y")
+    if X.data_ptr() == Y.data_ptr() and size > 0:
+        raise ValueError("X and Y must not overlap")
+    return _call("kron3d_batched_ex_f32_noalloc", n, *opc, float(alpha), *ptrs, px, float(beta), py, batch,
+                 _stream(stream))
 
 
 _ND_TYPES = {torch.float32: ("f32", MODE_F32), torch.float64: ("f64", MODE_F64),

@@ -6,6 +6,7 @@
 #include <atomic>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 
 #include "kron.h"
 #include "kron_runtime.hpp"
@@ -235,6 +236,37 @@ int ex3d_f32_call(int n, char opA, char opB, char opC, float alpha, const float*
   const float* P = static_cast<const float*>(ws);
   return finish_launch(beta != 0.0f ? kron::ex3d_f32(n, P, P + n * n, P + 2 * n * n, X, Y, batch, beta, stream)
                                      : kron::fwd3d_f32(n, P, P + n * n, P + 2 * n * n, X, Y, batch, stream, false));
+}
+
+// The allocation-free entry point's workspace: the three prepared n x n
+// FP32 factors of one call (3 KiB at n = 16).  Every device holds its own
+// copy for the life of the process.  Host code never passes the array's
+// name to a kernel: it is a host-side stand-in, not a device address.  The
+// device address is looked up once per device (with that device current)
+// and kept per device ordinal.
+constexpr size_t kNoAllocScratchBytes = 3 * KRON_MAX_N * KRON_MAX_N * sizeof(float);
+static __device__ __align__(256) float scratch[kNoAllocScratchBytes / sizeof(float)];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];
+
+// Device address of `scratch` on the current device; 0 or a hipError_t.
+int noalloc_scratch(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return (int)e;
+  if (dev < 0 || dev >= kMaxDevices) return (int)hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return (int)e;
+    if (!p) return (int)hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return 0;
 }
 
 }  // namespace
@@ -575,6 +607,18 @@ int kron3d_batched_ex_f32(int n, char opA, char opB, char opC, float alpha, cons
                           const float* C, const float* X, float beta, float* Y, int64_t batch, void* ws,
                           size_t ws_bytes, hipStream_t stream) {
   return ex3d_f32_call(n, opA, opB, opC, alpha, A, B, C, X, beta, Y, batch, ws, ws_bytes, stream);
+}
+
+// The allocation-free variant: the prepared factors go to this library's
+// own device array instead of a caller workspace.
+int kron3d_batched_ex_f32_noalloc(int n, char opA, char opB, char opC, float alpha, const float* A,
+                                  const float* B, const float* C, const float* X, float beta, float* Y,
+                                  int64_t batch, hipStream_t stream) {
+  if (n < 1 || n > KRON_MAX_N) return -1;
+  if ((size_t)3 * n * n * sizeof(float) > kNoAllocScratchBytes) return -1;  // beyond the array's capacity
+  void* ws = nullptr;
+  if (int rc = noalloc_scratch(&ws)) return rc;
+  return ex3d_f32_call(n, opA, opB, opC, alpha, A, B, C, X, beta, Y, batch, ws, kNoAllocScratchBytes, stream);
 }
 
 int kron3d_batched_ex_f64(int n, char opA, char opB, char opC, double alpha, const double* A, const double* B,
