@@ -30,7 +30,7 @@ PAPER_K20C = {("f32", 3, 16): 268, ("f32", 2, 16): 285, ("f32", 3, 10): 126, ("f
 # every library source and header: the counter-derived traffic of the
 # headline kernel is reported only for the code and flags it was taken on
 KERNEL_SOURCE_DIRS = ["paper_1304_7054_amd/csrc"]
-KERNEL_HEADERS = ["include/kron.h"]
+KERNEL_HEADERS = ["include/kron.h", "paper_1304_7054_amd/tuning/gfx950.json"]
 
 
 def parse():
@@ -44,12 +44,17 @@ def parse():
     p.add_argument("--only", default="", help="comma-separated names of the measurements to run after the "
                    "headline (see measurement_plan), e.g. grouped,grouped-backward")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    p.add_argument("--tune-headline", action="store_true",
+                   help="autotune the headline's launch shape on this device first (default: the shipped table)")
     p.add_argument("--summarize-profiles", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
                    help="read rocprofv3 outputs of this script (kernel trace, FETCH_SIZE, WRITE_SIZE runs "
                         "with --copy-calibration) and write the summary and traffic record under profiles/")
     p.add_argument("--summarize-trace", metavar="TRACE_DIR",
                    help="read a rocprofv3 --kernel-trace --stats run of the whole benchmark and write the per-kernel "
                         "summary profiles/bench_kernels.md")
+    p.add_argument("--summarize-counters", nargs="+", metavar="ARG",
+                   help="OUT_NAME TITLE COMMAND_FILE DIR [DIR ...]: per-kernel counter averages of rocprofv3 --pmc "
+                        "runs, written to profiles/OUT_NAME.md with the commands listed in COMMAND_FILE")
     p.add_argument("--copy-calibration", action="store_true",
                    help="first run three plain 1 GiB device copies (a kernel of known traffic for "
                         "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -109,10 +114,17 @@ def fn_for(mode, dim):
 DEVICE_WARM_S = 0.5
 
 
+LAST_TIMING = {}
+
+
 def time_launches(torch, fn, args, steps, warmup):
     """Run `steps` launches bracketed by synchronisation; HIP events around
     every launch on the stream it is issued on.  Returns (wall ms/step,
-    mean kernel ms, min kernel ms)."""
+    mean kernel ms, min kernel ms); the median is kept in LAST_TIMING.  The
+    Python garbage collector is held off during the timed launches: a
+    collection pause that outlasts the queued work would otherwise land
+    inside an event interval as idle device time."""
+    import gc
     stream = torch.cuda.current_stream()
     # bring the device to its steady clocks first (untimed), then the W warm-up steps
     t_end = time.perf_counter() + DEVICE_WARM_S
@@ -124,14 +136,21 @@ def time_launches(torch, fn, args, steps, warmup):
         fn(*args, stream=stream)
     torch.cuda.synchronize()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
-    t0 = time.perf_counter()
-    for a, b in ev:
-        a.record(stream)
-        fn(*args, stream=stream)
-        b.record(stream)
-    torch.cuda.synchronize()
-    wall = (time.perf_counter() - t0) * 1e3 / steps
+    gc_was = gc.isenabled()
+    gc.disable()
+    try:
+        t0 = time.perf_counter()
+        for a, b in ev:
+            a.record(stream)
+            fn(*args, stream=stream)
+            b.record(stream)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) * 1e3 / steps
+    finally:
+        if gc_was:
+            gc.enable()
     ks = [a.elapsed_time(b) for a, b in ev]
+    LAST_TIMING.update({"median_ms": float(np.median(ks)), "max_ms": float(np.max(ks))})
     return wall, float(np.mean(ks)), float(np.min(ks))
 
 
@@ -164,6 +183,7 @@ def measure(torch, mode, dim, n, batch, steps, warmup, seed):
     gbs = alg_bytes / (kmean * 1e-3) / 1e9
     err = sampled_error(torch, mode, dim, n, mats, X, Y, batch)
     out = {"mode": mode, "dim": dim, "n": n, "batch": batch, "ms": round(kmean, 4), "ms_min": round(kmin, 4),
+           "ms_median": round(LAST_TIMING["median_ms"], 4), "ms_max": round(LAST_TIMING["max_ms"], 4),
            "wall_ms_per_step": round(wall, 4), "gflops": round(gflops, 1), "gbs": round(gbs, 1),
            "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "alg_bytes": alg_bytes, "sampled_rel_err": err}
     k20 = PAPER_K20C.get((mode, dim, n))
@@ -175,16 +195,24 @@ def measure(torch, mode, dim, n, batch, steps, warmup, seed):
 
 
 def measure_copy(torch, steps, warmup):
-    """A plain 1 GiB device-to-device copy (torch copy_, 1 GiB read + 1 GiB
-    written) timed like the kernels: the achievable-bandwidth reference."""
+    """Plain 1 GiB device-to-device copies (1 GiB read + 1 GiB written) timed
+    like the kernels: the library's streaming copy (kron_copy_bytes, the same
+    16-byte non-temporal accesses as its kernels; the reference of
+    frac_of_copy) and torch's copy_ for context."""
+    import paper_1304_7054_amd as kron
     src = torch.ones(1 << 28, device="cuda")
     dst = torch.empty_like(src)
-    wall, kmean, kmin = time_launches(torch, lambda stream=None: dst.copy_(src), (), steps, warmup)
+    out = {"bytes": 2 * (1 << 30)}
+    for tag, fn in (("stream_copy", lambda stream=None: kron.kron_copy_bytes(src, dst, stream)),
+                    ("torch_copy", lambda stream=None: dst.copy_(src))):
+        wall, kmean, kmin = time_launches(torch, fn, (), steps, warmup)
+        gbs = 2 * (1 << 30) / (kmean * 1e-3) / 1e9
+        out[tag] = {"ms": round(kmean, 4), "gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+    assert bool(torch.equal(src, dst))
+    out["gbs"] = out["stream_copy"]["gbs"]
     del src, dst
     torch.cuda.empty_cache()
-    gbs = 2 * (1 << 30) / (kmean * 1e-3) / 1e9
-    return {"bytes": 2 * (1 << 30), "ms": round(kmean, 4), "gbs": round(gbs, 1),
-            "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+    return out
 
 
 def batch_errors(mode, n, mats_exact, X_dev, Y_dev, batch, chunk=4096):
@@ -244,7 +272,8 @@ def measure_precision(torch, steps, warmup):
         gbs = bytes_per * batch / (kmean * 1e-3) / 1e9
         rec = {"mode": mode, "dim": 3, "n": n, "batch": batch,
                "data": "log-uniform magnitudes in [1e-3, 1e3], random signs (A, B, C and X)",
-               "ms": round(kmean, 4), "ms_min": round(kmin, 4), "wall_ms_per_step": round(wall, 4),
+               "ms": round(kmean, 4), "ms_min": round(kmin, 4), "ms_median": round(LAST_TIMING["median_ms"], 4),
+               "ms_max": round(LAST_TIMING["max_ms"], 4), "wall_ms_per_step": round(wall, 4),
                "gflops": round(batch * flops_per_op(3, n) / (kmean * 1e-3) / 1e9, 1), "gbs": round(gbs, 1),
                "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "alg_bytes": bytes_per * batch}
         if mode == "bf16":
@@ -749,6 +778,33 @@ HEADLINE_KERNELS = ("kron::kron3d_stream_kernel<kron::ModeF32,", "kron::kron3d_k
 CALIBRATION_KERNEL = "__amd_rocclr_copyBuffer"
 
 
+def tune_headline(torch):
+    """Autotune the headline's launch shape on this device (kron_autotune:
+    every variant x workgroups-per-CU, three sweeps, lowest mean) on the
+    headline workload's own buffers, before anything is timed.  Returns the
+    choice."""
+    import paper_1304_7054_amd as kron
+    import workloads
+    n, batch = 16, workloads.BATCH_3D[16]
+    mats, X, Y = make_inputs(torch, 3, n, batch, "f32", 2)
+    t = time.perf_counter()
+    b, v, ms = kron.kron_autotune(kron.MODE_F32, 3, n, *mats, X, Y, batch, reps=10)
+    out = {"variant": v, "blocks_per_cu": b, "tune_ms": round(ms, 4), "tune_s": round(time.perf_counter() - t, 1)}
+    del mats, X, Y
+    torch.cuda.empty_cache()
+    print(f"# headline launch shape tuned on this device: {out}", file=sys.stderr, flush=True)
+    return out
+
+
+def launch_shape_record():
+    """The launch shape the headline ran with and the autotuned table it came from."""
+    import paper_1304_7054_amd as kron
+    from paper_1304_7054_amd import _binding
+    blocks, variant = kron.kron_get_launch(kron.MODE_F32, 3, 16)
+    return {"variant": variant, "blocks_per_cu": blocks, "table": _binding.APPLIED_TABLE["path"],
+            "table_entries": _binding.APPLIED_TABLE["entries"]}
+
+
 def headline_kernel_name():
     """The kernel the FP32 3-D n = 16 launch runs under the current launch table."""
     import paper_1304_7054_amd as kron
@@ -859,6 +915,44 @@ def summarize_trace(trace_dir):
     print("\n".join(lines))
 
 
+def summarize_counters(out_name, title, command, dirs):
+    """Per-kernel averages (per dispatch) of every counter collected in the
+    rocprofv3 --pmc runs under `dirs` (library kernels only), written to
+    profiles/<out_name>.md with the commands that made them."""
+    import csv
+    import glob
+    from collections import defaultdict
+    acc = defaultdict(lambda: defaultdict(list))
+    for d in dirs:
+        for path in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            with open(path) as f:
+                for r in csv.DictReader(f):
+                    name = r["Kernel_Name"]
+                    if "kron" not in name and "copyBuffer" not in name:
+                        continue
+                    acc[name][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    counters = sorted({c for k in acc.values() for c in k})
+    lines = [f"# {title}", "", "Counters are rocprofv3 --pmc readings averaged over the dispatches of each kernel "
+             "(FETCH_SIZE / WRITE_SIZE in KiB per dispatch, raw; the others summed over the device).", "",
+             "```", "export TMPDIR=/tmp", command.rstrip(), "```", "",
+             "| kernel | dispatches | " + " | ".join(counters) + " |",
+             "|---|---|" + "---|" * len(counters)]
+    for name in sorted(acc):
+        short = name.replace("void ", "")
+        if ">(" in short:
+            short = short[:short.index(">(") + 1]
+        elif short.endswith(")"):
+            short = short[:short.rfind("(")]
+        n = max(len(v) for v in acc[name].values())
+        vals = [f"{sum(acc[name][c]) / len(acc[name][c]):.4g}" if acc[name].get(c) else "" for c in counters]
+        lines.append(f"| `{short[:110]}` | {n} | " + " | ".join(vals) + " |")
+    lines.append("")
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    with open(os.path.join(ROOT, "profiles", out_name + ".md"), "w") as f:
+        f.write("\n".join(lines))
+    print("\n".join(lines))
+
+
 def _profile_markdown(out, stats):
     rows = sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:5]
     lines = [
@@ -951,6 +1045,11 @@ def main():
     if args.summarize_trace:
         summarize_trace(args.summarize_trace)
         return
+    if args.summarize_counters:
+        out_name, title, cmd_file, *dirs = args.summarize_counters
+        with open(cmd_file) as f:
+            summarize_counters(out_name, title, f.read(), dirs)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the batch splits into independent per-GPU shards with no communication)", file=sys.stderr)
@@ -971,6 +1070,9 @@ def main():
         torch.cuda.synchronize()
         del src, dst
         torch.cuda.empty_cache()
+    tuned = None
+    if args.tune_headline:
+        tuned = tune_headline(torch)
     head = measure(torch, "f32", 3, 16, workloads.BATCH_3D[16], args.steps, args.warmup, seed=2)
     copy = measure_copy(torch, max(10, args.steps // 2), args.warmup)
     others = []
@@ -987,7 +1089,8 @@ def main():
     roof = {"bound": "hbm", "achieved": head["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(head["gbs"] / HBM_PEAK_GBS, 4), "traffic": traffic_record(khash),
             "kernel": headline_kernel_name(), "alg_bytes_per_launch": head["alg_bytes"],
-            "kernel_ms": head["ms"], "copy_1gib": copy,
+            "kernel_ms": head["ms"], "launch_shape": dict(launch_shape_record(), tuned_on_device=tuned),
+            "copy_1gib": copy,
             "frac_of_copy": round(head["gbs"] / copy["gbs"], 4)}
     line = {
         "metric": "Kron-action GFLOP/s + % HBM roofline, 3-D n=16 FP32: plain vs bf16x3 MFMA",

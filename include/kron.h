@@ -504,6 +504,16 @@ size_t kron_grouped_backward_workspace_size(const kron_group_grad_t* groups, int
 int kron_grouped_backward(const kron_group_grad_t* groups, int ngroups, void* ws, size_t ws_bytes,
                           hipStream_t stream);
 
+/* ---- measurement reference ----------------------------------------------------- */
+
+/* Copies `bytes` bytes from src to dst with the memory access pattern of this
+   library's kernels (16-byte non-temporal loads and stores, a persistent
+   grid): the achievable device-memory bandwidth the Kronecker kernels are
+   compared with.  src and dst: 16-byte aligned device pointers that must not
+   overlap; bytes: a multiple of 16.  Returns 0, -1 (src), -2 (dst), -3
+   (bytes) or a positive hipError_t; asynchronous on `stream`. */
+int kron_copy_bytes(const void* src, void* dst, size_t bytes, hipStream_t stream);
+
 /* ---- launch shape ----------------------------------------------------------- */
 
 /* How the kernels for (mode, dim, n) are launched: `blocks_per_cu` 256-thread
@@ -528,10 +538,12 @@ int kron_get_launch(int mode, int dim, int n, int* blocks_per_cu, int* variant);
 /* Autotuner: time every launch shape (variants x 0..4 workgroups per CU) of
    (mode, dim, n) on the caller's device buffers (A, B, C, X read; Y is
    overwritten; C may be NULL for dim 2; element type as for the mode's
-   entry points), `reps` timed launches each on `stream` with HIP events,
-   keep the fastest in the launch-shape table and report it (any out
-   pointer may be NULL).  Synchronises `stream`.  On error the entry is
-   reset to the built-in default. */
+   entry points), `reps` timed launches each on `stream` with HIP events, in
+   three sweeps over all shapes (forward, reverse, forward; three untimed
+   launches before each timing), keep the shape with the lowest mean time in
+   the launch-shape table and report it with that mean (any out pointer may
+   be NULL).  Synchronises `stream`.  On error the entry is reset to the
+   built-in default. */
 int kron_autotune(int mode, int dim, int n, const void* A, const void* B, const void* C,
                   const void* X, void* Y, int64_t batch, int reps, hipStream_t stream,
                   int* best_blocks, int* best_variant, float* best_ms);

@@ -72,6 +72,7 @@ from ._binding import (  # noqa: F401
     kron_grouped_launch,
     kron_grouped_prepare,
     kron_grouped_workspace_size,
+    kron_copy_bytes,
     kron_grouped_backward,
     kron_grouped_backward_workspace_size,
     KronGroupGrad,

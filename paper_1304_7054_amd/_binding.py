@@ -139,6 +139,8 @@ def lib():
             f.argtypes = [ctypes.c_int, ip, ip, cp, sc, ctypes.POINTER(ctypes.c_void_p), ip, lp, ctypes.c_void_p, sc,
                           ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
             f.restype = ctypes.c_int
+        L.kron_copy_bytes.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+        L.kron_copy_bytes.restype = ctypes.c_int
         L.kron_grouped_backward_workspace_size.argtypes = [ctypes.POINTER(KronGroupGrad), ctypes.c_int]
         L.kron_grouped_backward_workspace_size.restype = ctypes.c_size_t
         L.kron_grouped_backward.argtypes = [ctypes.POINTER(KronGroupGrad), ctypes.c_int, ctypes.c_void_p,
@@ -824,6 +826,16 @@ def kron_grouped_backward(groups, ws=None, stream=None):
         ws = _scratch(need, dev, stream)
     pw = _arr(ws, torch.uint8, need, "workspace")
     return _call("kron_grouped_backward", arr, k, pw, ws.numel(), _stream(stream))
+
+
+def kron_copy_bytes(src, dst, stream=None):
+    """Streaming copy of src into dst (same byte size, 16-byte multiples): the
+    bandwidth reference of the measurements."""
+    nb = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nb or not (src.is_contiguous() and dst.is_contiguous()):
+        raise ValueError("src and dst must be contiguous and of the same byte size")
+    return _call("kron_copy_bytes", ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), nb,
+                 _stream(stream))
 
 
 def kron_grouped_workspace_size(groups):

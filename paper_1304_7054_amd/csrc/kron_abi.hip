@@ -694,13 +694,24 @@ int kron_autotune(int mode, int dim, int n, const void* A, const void* B, const 
   for (int v = 0; v <= (dim == 3 ? 10 : 3); ++v)
     if (dim == 2 || (v == 8 ? n != 16 : v < 8 || n == 16)) vars[nvar++] = v;
   const int blocks[] = {0, 1, 2, 3, 4};
-  float best = 3.4e38f;
-  int bb = 0, bv = 0, rc = 0;
-  for (int vi = 0; vi < nvar && rc == 0; ++vi) {
-    const int v = vars[vi];
-    for (int b : blocks) {
+  constexpr int kNB = sizeof(blocks) / sizeof(blocks[0]);
+  // Every shape is timed in three sweeps (forward, reverse, forward) and
+  // scored by its mean: clocks that are still rising during the first shapes
+  // of a sweep cannot decide the choice, and neither can one lucky timing of
+  // a shape whose time varies from launch to launch.  Each timing follows
+  // three untimed launches of the same shape.
+  constexpr int kSweeps = 3;
+  float times[11 * kNB];
+  for (float& t : times) t = 0.f;
+  int rc = 0;
+  const int nshape = nvar * kNB;
+  for (int sweep = 0; sweep < kSweeps && rc == 0; ++sweep) {
+    for (int q = 0; q < nshape && rc == 0; ++q) {
+      const int idx = sweep % 2 == 0 ? q : nshape - 1 - q;
+      const int v = vars[idx / kNB], b = blocks[idx % kNB];
       kron::set_launch_shape(mode, dim, n, b, v);
-      if ((rc = run()) != 0) break;  // warm-up (code object load)
+      for (int w = 0; w < 3 && rc == 0; ++w) rc = run();  // warm-up (first: code object load)
+      if (rc != 0) break;
       if ((e = hipEventRecord(e0, stream)) != hipSuccess) { rc = (int)e; break; }
       for (int r = 0; r < reps && rc == 0; ++r) rc = run();
       if (rc != 0) break;
@@ -710,10 +721,17 @@ int kron_autotune(int mode, int dim, int n, const void* A, const void* B, const 
       }
       float ms = 0.f;
       if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) { rc = (int)e; break; }
-      ms /= (float)reps;
-      if (ms < best) { best = ms; bb = b; bv = v; }
+      times[idx] += ms / (float)reps / (float)kSweeps;
     }
   }
+  float best = 3.4e38f;
+  int bb = 0, bv = 0;
+  for (int idx = 0; idx < nshape; ++idx)
+    if (times[idx] < best) {
+      best = times[idx];
+      bv = vars[idx / kNB];
+      bb = blocks[idx % kNB];
+    }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc != 0) {

@@ -135,10 +135,18 @@ __device__ __attribute__((noinline)) int64_t run_group_2d(const GroupDesc& gd, i
     using S = Staged2D<M, N, false>;
     static_assert(S::kSpan * sizeof(io_t) <= kGroupSlice2 * sizeof(float), "2-D span exceeds the wavefront's LDS");
     const S st(static_cast<const io_t*>(gd.A), static_cast<const io_t*>(gd.B), L, g);
+    const int lane = threadIdx.x & 63;
+    // the next unit of the chunk is loaded into registers while the current
+    // one is computed and written out (as in the single-group kernel)
+    RunPrefetch<io_t, kT * S::kElems> pf;
     do {
       const unsigned long long nx = cl.issue();
-      for (int64_t u = ct.first(c) - u0, ue = ct.first(c + 1) - u0; u < ue; ++u)
-        staged2d_tiles<S>(st, slice, X, Y, u * kT, ntiles, gd.count, threadIdx.x & 63);
+      int64_t u = ct.first(c) - u0;
+      const int64_t ue = ct.first(c + 1) - u0;
+      if (u < ue) pf.issue(X + u * kT * S::kElems, span_elems<S>(u * kT, ntiles, gd.count), lane);
+      for (; u < ue; ++u)
+        staged2d_tiles<S, true>(st, slice, X, Y, u * kT, ntiles, gd.count, lane, &pf,
+                                u + 1 < ue ? (u + 1) * kT : ntiles);
       c = Claim::value(nx);
     } while (c < ct.nchunks && ct.first(c) < u1);
   } else {
@@ -186,10 +194,20 @@ __device__ __attribute__((noinline)) int64_t run_group_3d(const GroupDesc& gd, i
     using S = Staged3D<M, N, false>;
     static_assert(S::kSlice * sizeof(io_t) <= kGroupSlice3 * sizeof(float), "3-D slice exceeds the wavefront's LDS");
     const S st(A, B, C, L, g);
+    const int lane = threadIdx.x & 63;
+    // the next tile of the chunk is loaded into registers while the current
+    // one is computed (up to 8 vectors per lane; larger tiles copy the rest
+    // when they are committed)
+    RunPrefetch<io_t, S::kElems> pf;
+    auto ops_of = [&](int64_t t) { return (int)((gd.count - t * S::kOps) < S::kOps ? gd.count - t * S::kOps : S::kOps); };
     do {
       const unsigned long long nx = cl.issue();
-      for (int64_t t = ct.first(c) - u0, te = ct.first(c + 1) - u0; t < te; ++t)
-        staged3d_tile(st, slice, X + t * S::kElems, Y + t * S::kElems, gd.count - t * S::kOps, threadIdx.x & 63);
+      int64_t t = ct.first(c) - u0;
+      const int64_t te = ct.first(c + 1) - u0;
+      if (t < te) pf.issue(X + t * S::kElems, ops_of(t) * S::E, lane);
+      for (; t < te; ++t)
+        staged3d_tile<S, true>(st, slice, X + t * S::kElems, Y + t * S::kElems, gd.count - t * S::kOps, lane, &pf,
+                               t + 1 < te ? X + (t + 1) * S::kElems : nullptr, gd.count - (t + 1) * S::kOps);
       c = Claim::value(nx);
     } while (c < ct.nchunks && ct.first(c) < u1);
   } else {

@@ -32,6 +32,7 @@ namespace kron {
 namespace {
 
 constexpr int kNdMaxDim = 8;
+constexpr int kNdSubTiles = 1;  // 16-column sub-tiles per tile of kron_mode_kernel (4 measured no faster)
 
 // Offset of column c of a pass: its digits, fastest first, each times its
 // stride (digit j = (c / prod_{i<j} mod_i) % mod_j; the last digit takes the
@@ -55,6 +56,69 @@ __device__ __forceinline__ int64_t nd_offset(const NdIndex& ix, int64_t c) {
   return off + c * ix.stride[ix.nlev - 1];
 }
 
+// Digits of a column, kept up to date by additions as a wavefront walks its
+// tiles (a 64-bit division per tile would cost more than the tile's MFMAs).
+struct Digits {
+  int64_t d[3];
+  __device__ __forceinline__ void set(const NdIndex& ix, int64_t c) {
+    for (int j = 0; j < ix.nlev - 1; ++j) {
+      d[j] = c % ix.mod[j];
+      c /= ix.mod[j];
+    }
+    d[ix.nlev - 1] = c;
+  }
+  // column += k (k >= 0), carrying into the slower digits
+  __device__ __forceinline__ void add(const NdIndex& ix, int64_t k) {
+    d[0] += k;
+    if (ix.nlev == 1) return;
+    while (d[0] >= ix.mod[0]) {
+      d[0] -= ix.mod[0];
+      ++d[1];
+    }
+    if (ix.nlev == 2) return;
+    while (d[1] >= ix.mod[1]) {
+      d[1] -= ix.mod[1];
+      ++d[2];
+    }
+  }
+  __device__ __forceinline__ int64_t offset(const NdIndex& ix) const {
+    int64_t off = d[0] * ix.stride[0];
+    for (int j = 1; j < ix.nlev; ++j) off += d[j] * ix.stride[j];
+    return off;
+  }
+};
+
+// A wavefront's tiles are one contiguous range; within it the tile
+// coordinates (row chunk fastest, then column chunk, then group) advance by
+// additions.
+struct TileWalk {
+  int64_t t, t1, grp, ch;
+  int ic;
+  __device__ __forceinline__ TileWalk(int64_t ntiles, int rows, int64_t chunks, int64_t wave, int64_t nwaves) {
+    const int64_t per = (ntiles + nwaves - 1) / nwaves;
+    t = wave * per;
+    t1 = t + per < ntiles ? t + per : ntiles;
+    ic = 0;
+    grp = ch = 0;
+    if (t < t1) {
+      ic = (int)(t % rows);
+      const int64_t ct = t / rows;
+      grp = ct / chunks;
+      ch = ct % chunks;
+    }
+  }
+  // next tile; returns 0 (same columns), 1 (next chunk of the group) or 2 (next group)
+  __device__ __forceinline__ int next(int rows, int64_t chunks) {
+    ++t;
+    if (++ic < rows) return 0;
+    ic = 0;
+    if (++ch < chunks) return 1;
+    ch = 0;
+    ++grp;
+    return 2;
+  }
+};
+
 // One mode product.  Element counts and offsets are in elements (a complex
 // element is one unit; its two parts follow each other in memory).
 struct NdPass {
@@ -68,6 +132,7 @@ struct NdPass {
   int conjx;      // conjugate the input elements (op(X) = X^* of the 2-D interface)
   NdIndex in, out;
   int64_t cols;   // columns per group (a group shares one factor)
+  int64_t cols_groups;  // number of groups
   int64_t chunks; // 16-column chunks per group
   int rows;       // 16-row chunks of the output index
 };
@@ -108,108 +173,336 @@ __device__ __forceinline__ void st_elem(T* p, int64_t e, T re, T im) {
   }
 }
 
-// kDataA: the data is the MFMA's A operand (post == 1); otherwise B.
-// kBeta: Out <- alpha * product + beta * Out (the last pass); otherwise
-// Out <- alpha * product.
-template <typename T, bool kC, bool kDataA, bool kBeta>
-__global__ __launch_bounds__(kBlock) void kron_mode_kernel(NdPass P, int64_t ntiles, T ar, T ai, T br, T bi) {
+// NS consecutive scalars at p (p aligned to min(16, NS * sizeof(T)) bytes),
+// in 16-byte (or, below 16 bytes, NS-scalar) non-temporal vector accesses.
+template <typename T, int NS>
+__device__ __forceinline__ void ldv(const T* p, T (&o)[NS]) {
+  constexpr int W = (NS * sizeof(T) >= 16) ? 16 / (int)sizeof(T) : NS;
+  typedef T V __attribute__((ext_vector_type(W)));
+#pragma unroll
+  for (int q = 0; q < NS / W; ++q) {
+    const V v = __builtin_nontemporal_load(in_global(reinterpret_cast<const V*>(p)) + q);
+#pragma unroll
+    for (int e = 0; e < W; ++e) o[q * W + e] = v[e];
+  }
+}
+
+template <typename T, int NS>
+__device__ __forceinline__ void stv(T* p, const T (&o)[NS]) {
+  constexpr int W = (NS * sizeof(T) >= 16) ? 16 / (int)sizeof(T) : NS;
+  typedef T V __attribute__((ext_vector_type(W)));
+#pragma unroll
+  for (int q = 0; q < NS / W; ++q) {
+    V v;
+#pragma unroll
+    for (int e = 0; e < W; ++e) v[e] = o[q * W + e];
+    __builtin_nontemporal_store(v, in_global(reinterpret_cast<V*>(p)) + q);
+  }
+}
+
+// op(F)(i, a) of the stored factor (zero outside m x n); complex parts in
+// fr, fi with the conjugation of op 'C' applied.
+template <typename T, bool kC>
+__device__ __forceinline__ void factor_entry(const NdPass& P, const T* F, int i, int a, T& fr, T& fi) {
+  fr = T(0);
+  fi = T(0);
+  if (i < P.m && a < P.n) {
+    const int64_t e = P.op == 0 ? i + (int64_t)P.ld * a : a + (int64_t)P.ld * i;
+    if constexpr (kC) {
+      fr = in_global(F)[2 * e];
+      fi = in_global(F)[2 * e + 1];
+      if (P.op == 2) fi = -fi;
+    } else {
+      fr = in_global(F)[e];
+    }
+  }
+}
+
+// Dense passes whose faster extent `post` is a multiple of kW: a tile is 16
+// output rows by 16 * kW consecutive columns, and lane L owns the kW columns
+// cb + kW * L .. + kW - 1, which lie in one u and are consecutive in memory,
+// so they are loaded and stored as vectors.  Each of them is one MFMA's B
+// operand (the factor is shared), so the tile is kW (complex: 4 kW) MFMAs
+// per contraction step.  X and Y are 16-byte aligned.
+template <typename T, bool kC, int kW, bool kBeta>
+__global__ __launch_bounds__(kBlock) void kron_mode_wide_kernel(NdPass P, int64_t ntiles, T ar, T ai, T br, T bi) {
   using A = NdAcc<T>;
   using acc_t = typename A::type;
+  constexpr int kS = kC ? 2 : 1;   // scalars per element
+  constexpr int NS = kW * kS;      // scalars per lane and row
   const T* __restrict__ X = static_cast<const T*>(P.X);
   T* __restrict__ Y = static_cast<T*>(P.Y);
   const int l = threadIdx.x & 63, L = l & 15, g = l >> 4;
   const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * kBlock) >> 6;
   const int nk = (P.n + 15) / 16;
-  for (int64_t t = wave; t < ntiles; t += nwaves) {
-    const int ic = (int)(t % P.rows);
-    const int64_t ct = t / P.rows;
-    const int64_t grp = ct / P.chunks;
-    const int64_t cb = grp * P.cols + (ct % P.chunks) * 16;  // first column of the tile
-    const int64_t cend = (grp + 1) * P.cols;
-    const T* F = static_cast<const T*>(P.F) + grp * P.ldfp * (kC ? 2 : 1);
-    // The 16 columns of a tile usually share every digit but the fastest
-    // (cb's fastest digit + 15 stays below its radix): one offset for the
-    // tile plus the lane's step.  Otherwise every column is decomposed.
-    const bool fast_in = P.in.nlev == 1 || (cb % P.in.mod[0]) + 16 <= P.in.mod[0];
-    const bool fast_out = P.out.nlev == 1 || (cb % P.out.mod[0]) + 16 <= P.out.mod[0];
-    const int64_t in0 = nd_offset(P.in, cb), out0 = nd_offset(P.out, cb);
-    // the column this lane loads (both mappings: column cb + L)
-    const int64_t cl = cb + L;
-    const bool colok = cl < cend;
-    const int64_t xb = fast_in ? in0 + L * P.in.stride[0] : nd_offset(P.in, cl);
-    const int fi_row = 16 * ic + L;  // factor row held by this lane
-    acc_t dr = {0, 0, 0, 0}, di = {0, 0, 0, 0};
+  const int64_t post = P.in.mod[0];
+  TileWalk w(ntiles, P.rows, P.chunks, wave, nwaves);
+  Digits dc;  // digits (v, u) of the tile's first column
+  if (w.t < w.t1) dc.set(P.in, w.grp * P.cols + w.ch * (16 * kW));
+  for (; w.t < w.t1;) {
+    const int ic = w.ic;
+    const int64_t grp = w.grp;
+    const int64_t cl = grp * P.cols + w.ch * (16 * kW) + kW * L;  // this lane's first column
+    const bool colok = cl < (grp + 1) * P.cols;
+    const T* F = static_cast<const T*>(P.F) + grp * P.ldfp * kS;
+    // this lane's (u, v): the tile's digits plus kW * L columns
+    int64_t u = dc.d[1], v0 = dc.d[0] + kW * L;
+    if (v0 >= post) {
+      const uint32_t q = (uint32_t)((uint64_t)v0 / (uint64_t)post);
+      u += q;
+      v0 -= (int64_t)q * post;
+    }
+    const int64_t xb = u * P.n * post + v0, yb = u * P.m * post + v0;
+    acc_t dr[kW], di[kW];
+#pragma unroll
+    for (int j = 0; j < kW; ++j) {
+      dr[j] = acc_t{0, 0, 0, 0};
+      di[j] = acc_t{0, 0, 0, 0};
+    }
     for (int kc = 0; kc < nk; ++kc) {
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         const int a = 16 * kc + 4 * g + s;
-        T xr = 0, xi = 0, fr = 0, fi = 0;
+        T x[NS];
         if (colok && a < P.n) {
-          ld_elem<T, kC>(X, xb + (int64_t)a * P.in.along, xr, xi);
-          if (kC && P.conjx) xi = -xi;
-        }
-        if (fi_row < P.m && a < P.n) {
-          const int64_t e = P.op == 0 ? fi_row + (int64_t)P.ld * a : a + (int64_t)P.ld * fi_row;
-          if constexpr (kC) {
-            fr = in_global(F)[2 * e];
-            fi = in_global(F)[2 * e + 1];
-            if (P.op == 2) fi = -fi;
-          } else {
-            fr = in_global(F)[e];
-          }
-        }
-        if constexpr (kDataA) {
-          dr = A::mma(xr, fr, dr);
-          if constexpr (kC) {
-            dr = A::mma(xi, -fi, dr);
-            di = A::mma(xi, fr, di);
-            di = A::mma(xr, fi, di);
-          }
+          ldv<T, NS>(X + (xb + (int64_t)a * post) * kS, x);
         } else {
-          dr = A::mma(fr, xr, dr);
+#pragma unroll
+          for (int q = 0; q < NS; ++q) x[q] = T(0);
+        }
+        T fr, fi;
+        factor_entry<T, kC>(P, F, 16 * ic + L, a, fr, fi);
+#pragma unroll
+        for (int j = 0; j < kW; ++j) {
           if constexpr (kC) {
-            dr = A::mma(-fi, xi, dr);
-            di = A::mma(fr, xi, di);
-            di = A::mma(fi, xr, di);
+            dr[j] = A::mma(fr, x[2 * j], dr[j]);
+            dr[j] = A::mma(-fi, x[2 * j + 1], dr[j]);
+            di[j] = A::mma(fr, x[2 * j + 1], di[j]);
+            di[j] = A::mma(fi, x[2 * j], di[j]);
+          } else {
+            dr[j] = A::mma(fr, x[j], dr[j]);
           }
         }
       }
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int i = kDataA ? 16 * ic + L : 16 * ic + A::drow(g, r);
-      const int j = kDataA ? A::drow(g, r) : L;  // column of the tile
-      if (i >= P.m || cb + j >= cend) continue;
-      const int64_t e = (fast_out ? out0 + j * P.out.stride[0] : nd_offset(P.out, cb + j)) + (int64_t)i * P.out.along;
-      T yr = ar * dr[r] - ai * di[r];
-      T yi = ar * di[r] + ai * dr[r];
-      if constexpr (kBeta) {
-        T or_, oi;
-        ld_elem<T, kC>(Y, e, or_, oi);
-        yr = yr + (br * or_ - bi * oi);
-        yi = yi + (br * oi + bi * or_);
+      const int i = 16 * ic + A::drow(g, r);
+      if (i >= P.m || !colok) continue;
+      T* yp = Y + (yb + (int64_t)i * post) * kS;
+      T o[NS];
+#pragma unroll
+      for (int j = 0; j < kW; ++j) {
+        const T re = dr[j][r], im = kC ? di[j][r] : T(0);
+        o[j * kS] = ar * re - ai * im;
+        if constexpr (kC) o[j * kS + 1] = ar * im + ai * re;
       }
-      st_elem<T, kC>(Y, e, yr, yi);
+      if constexpr (kBeta) {
+        T old[NS];
+        ldv<T, NS>(yp, old);
+#pragma unroll
+        for (int j = 0; j < kW; ++j) {
+          if constexpr (kC) {
+            const T orr = old[2 * j], oi = old[2 * j + 1];
+            o[2 * j] += br * orr - bi * oi;
+            o[2 * j + 1] += br * oi + bi * orr;
+          } else {
+            o[j] += br * old[j];
+          }
+        }
+      }
+      stv<T, NS>(yp, o);
+    }
+    const int step = w.next(P.rows, P.chunks);
+    if (step == 1) dc.add(P.in, 16 * kW);
+    else if (step == 2 && w.t < w.t1) dc.set(P.in, w.grp * P.cols);
+  }
+}
+
+// kDataA: the data is the MFMA's A operand (post == 1); otherwise B.
+// kBeta: Out <- alpha * product + beta * Out (the last pass); otherwise
+// Out <- alpha * product.
+// kVecA (kDataA, dense input, n a multiple of 4, X 16-byte aligned): the
+// four contraction indices 4g .. 4g + 3 of a lane are consecutive in memory
+// and come in as one vector.
+template <typename T, bool kC, bool kDataA, bool kBeta, bool kVecA>
+__global__ __launch_bounds__(kBlock) void kron_mode_kernel(NdPass P, int64_t ntiles, T ar, T ai, T br, T bi) {
+  static_assert(!kVecA || kDataA, "vector loads of the A operand");
+  using A = NdAcc<T>;
+  using acc_t = typename A::type;
+  constexpr int kS = kC ? 2 : 1;
+  constexpr int kU = kNdSubTiles;  // 16-column sub-tiles per tile (more loads in flight per wavefront)
+  constexpr int kCols = 16 * kU;
+  const T* __restrict__ X = static_cast<const T*>(P.X);
+  T* __restrict__ Y = static_cast<T*>(P.Y);
+  const int l = threadIdx.x & 63, L = l & 15, g = l >> 4;
+  const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * kBlock) >> 6;
+  const int nk = (P.n + 15) / 16;
+  TileWalk w(ntiles, P.rows, P.chunks, wave, nwaves);
+  Digits din, dout;
+  if (w.t < w.t1) {
+    din.set(P.in, w.grp * P.cols + w.ch * kCols);
+    dout.set(P.out, w.grp * P.cols + w.ch * kCols);
+  }
+  for (; w.t < w.t1;) {
+    const int ic = w.ic;
+    const int64_t grp = w.grp;
+    const int64_t cb = grp * P.cols + w.ch * kCols;  // first column of the tile
+    const int64_t cend = (grp + 1) * P.cols;
+    const T* F = static_cast<const T*>(P.F) + grp * P.ldfp * kS;
+    // The columns of a tile usually share every digit but the fastest (cb's
+    // fastest digit + kCols - 1 stays below its radix): one offset for the
+    // tile plus the column's step.  Otherwise every column is decomposed.
+    const bool fast_in = P.in.nlev == 1 || din.d[0] + kCols <= P.in.mod[0];
+    const bool fast_out = P.out.nlev == 1 || dout.d[0] + kCols <= P.out.mod[0];
+    const int64_t in0 = din.offset(P.in), out0 = dout.offset(P.out);
+    // sub-tile j: columns cb + 16 j .. + 15; this lane loads column cb + 16 j + L
+    bool colok[kU];
+    int64_t xb[kU];
+#pragma unroll
+    for (int j = 0; j < kU; ++j) {
+      const int64_t cl = cb + 16 * j + L;
+      colok[j] = cl < cend;
+      xb[j] = fast_in ? in0 + (16 * j + L) * P.in.stride[0] : (colok[j] ? nd_offset(P.in, cl) : 0);
+    }
+    const int fi_row = 16 * ic + L;  // factor row held by this lane
+    acc_t dr[kU], di[kU];
+#pragma unroll
+    for (int j = 0; j < kU; ++j) {
+      dr[j] = acc_t{0, 0, 0, 0};
+      di[j] = acc_t{0, 0, 0, 0};
+    }
+    for (int kc = 0; kc < nk; ++kc) {
+      // the operands of every sub-tile first (loads in flight together)
+      T xv[kU][4 * kS];
+#pragma unroll
+      for (int j = 0; j < kU; ++j) {
+        if constexpr (kVecA) {
+          if (colok[j] && 16 * kc + 4 * g < P.n) {
+            ldv<T, 4 * kS>(X + (xb[j] + 16 * kc + 4 * g) * kS, xv[j]);
+          } else {
+#pragma unroll
+            for (int q = 0; q < 4 * kS; ++q) xv[j][q] = T(0);
+          }
+        } else {
+#pragma unroll
+          for (int s = 0; s < 4; ++s) {
+            const int a = 16 * kc + 4 * g + s;
+            T xr = 0, xi = 0;
+            if (colok[j] && a < P.n) ld_elem<T, kC>(X, xb[j] + (int64_t)a * P.in.along, xr, xi);
+            xv[j][s * kS] = xr;
+            if constexpr (kC) xv[j][s * kS + 1] = xi;
+          }
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int a = 16 * kc + 4 * g + s;
+        T fr, fi;
+        factor_entry<T, kC>(P, F, fi_row, a, fr, fi);
+#pragma unroll
+        for (int j = 0; j < kU; ++j) {
+          const T xr = xv[j][s * kS];
+          T xi = T(0);
+          if constexpr (kC) xi = P.conjx ? -xv[j][s * kS + 1] : xv[j][s * kS + 1];
+          if constexpr (kDataA) {
+            dr[j] = A::mma(xr, fr, dr[j]);
+            if constexpr (kC) {
+              dr[j] = A::mma(xi, -fi, dr[j]);
+              di[j] = A::mma(xi, fr, di[j]);
+              di[j] = A::mma(xr, fi, di[j]);
+            }
+          } else {
+            dr[j] = A::mma(fr, xr, dr[j]);
+            if constexpr (kC) {
+              dr[j] = A::mma(-fi, xi, dr[j]);
+              di[j] = A::mma(fr, xi, di[j]);
+              di[j] = A::mma(fi, xr, di[j]);
+            }
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kU; ++j) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = kDataA ? 16 * ic + L : 16 * ic + A::drow(g, r);
+        const int jc = 16 * j + (kDataA ? A::drow(g, r) : L);  // column of the tile
+        if (i >= P.m || cb + jc >= cend) continue;
+        const int64_t e =
+            (fast_out ? out0 + jc * P.out.stride[0] : nd_offset(P.out, cb + jc)) + (int64_t)i * P.out.along;
+        T yr = ar * dr[j][r] - ai * di[j][r];
+        T yi = ar * di[j][r] + ai * dr[j][r];
+        if constexpr (kBeta) {
+          T or_, oi;
+          ld_elem<T, kC>(Y, e, or_, oi);
+          yr = yr + (br * or_ - bi * oi);
+          yi = yi + (br * oi + bi * or_);
+        }
+        st_elem<T, kC>(Y, e, yr, yi);
+      }
+    }
+    const int step = w.next(P.rows, P.chunks);
+    if (step == 1) {
+      din.add(P.in, kCols);
+      dout.add(P.out, kCols);
+    } else if (step == 2 && w.t < w.t1) {
+      din.set(P.in, w.grp * P.cols);
+      dout.set(P.out, w.grp * P.cols);
     }
   }
 }
 
-template <typename T, bool kC, bool kDataA, bool kBeta>
+template <typename T, bool kC, bool kDataA, bool kBeta, bool kVecA>
 void launch_mode(const NdPass& P, int64_t ntiles, T ar, T ai, T br, T bi, hipStream_t stream) {
-  auto k = kron_mode_kernel<T, kC, kDataA, kBeta>;
+  auto k = kron_mode_kernel<T, kC, kDataA, kBeta, kVecA>;
   hipLaunchKernelGGL(k, dim3(grid_blocks(ntiles, occupancy_blocks(k), 0)), dim3(kBlock), 0, stream, P, ntiles, ar, ai,
                      br, bi);
 }
 
-template <typename T, bool kC>
-void run_pass(const NdPass& P, int64_t ntiles, bool data_a, bool beta, T ar, T ai, T br, T bi, hipStream_t s) {
-  if (data_a) {
-    if (beta) launch_mode<T, kC, true, true>(P, ntiles, ar, ai, br, bi, s);
-    else launch_mode<T, kC, true, false>(P, ntiles, ar, ai, br, bi, s);
+template <typename T, bool kC, int kW, bool kBeta>
+void launch_wide(NdPass P, T ar, T ai, T br, T bi, hipStream_t stream) {
+  P.chunks = (P.cols + 16 * kW - 1) / (16 * kW);
+  const int64_t ntiles = (P.cols > 0 ? P.cols_groups : 0) * P.chunks * P.rows;
+  auto k = kron_mode_wide_kernel<T, kC, kW, kBeta>;
+  hipLaunchKernelGGL(k, dim3(grid_blocks(ntiles, occupancy_blocks(k), 0)), dim3(kBlock), 0, stream, P, ntiles, ar, ai,
+                     br, bi);
+}
+
+template <typename T, bool kC, bool kBeta>
+void run_pass_b(const NdPass& P, int64_t ntiles, bool dense, T ar, T ai, T br, T bi, hipStream_t s) {
+  const int64_t post = P.in.nlev == 2 ? P.in.mod[0] : 1;
+  const bool aligned = ((reinterpret_cast<uintptr_t>(P.X) | reinterpret_cast<uintptr_t>(P.Y)) & 15) == 0;
+  if (dense && aligned && post % 4 == 0) {
+    launch_wide<T, kC, 4, kBeta>(P, ar, ai, br, bi, s);
+  } else if (dense && aligned && post % 2 == 0) {
+    launch_wide<T, kC, 2, kBeta>(P, ar, ai, br, bi, s);
   } else {
-    if (beta) launch_mode<T, kC, false, true>(P, ntiles, ar, ai, br, bi, s);
-    else launch_mode<T, kC, false, false>(P, ntiles, ar, ai, br, bi, s);
+    launch_mode<T, kC, false, kBeta, false>(P, ntiles, ar, ai, br, bi, s);
+  }
+}
+
+// One pass: the data as A operand when post == 1 (vector loads when the input
+// is dense, n is a multiple of 4 and X 16-byte aligned), else as B operand
+// (the wide tiles when both sides are dense, aligned, and post allows).
+template <typename T, bool kC>
+void run_pass(const NdPass& P, int64_t ntiles, bool data_a, bool dense_in, bool dense_out, bool beta, T ar, T ai,
+              T br, T bi, hipStream_t s) {
+  if (data_a) {
+    const bool vec = dense_in && P.n % 4 == 0 && (reinterpret_cast<uintptr_t>(P.X) & 15) == 0;
+    if (vec) {
+      if (beta) launch_mode<T, kC, true, true, true>(P, ntiles, ar, ai, br, bi, s);
+      else launch_mode<T, kC, true, false, true>(P, ntiles, ar, ai, br, bi, s);
+    } else {
+      if (beta) launch_mode<T, kC, true, true, false>(P, ntiles, ar, ai, br, bi, s);
+      else launch_mode<T, kC, true, false, false>(P, ntiles, ar, ai, br, bi, s);
+    }
+  } else {
+    if (beta) run_pass_b<T, kC, true>(P, ntiles, dense_in && dense_out, ar, ai, br, bi, s);
+    else run_pass_b<T, kC, false>(P, ntiles, dense_in && dense_out, ar, ai, br, bi, s);
   }
 }
 
@@ -362,11 +655,14 @@ int nd_run(int d, const int* m, const int* n, const char* ops, T ar, T ai, const
     const bool shared = ldfp[k] == 0;
     P.cols = shared ? batch * pre * post : pre * post;
     const int64_t groups = shared ? 1 : batch;
-    P.chunks = (P.cols + 15) / 16;
+    P.cols_groups = groups;
+    P.chunks = (P.cols + 16 * kNdSubTiles - 1) / (16 * kNdSubTiles);
     P.rows = (m[k] + 15) / 16;
     const int64_t ntiles = groups * P.chunks * P.rows;
     const bool last = k == 0;
-    run_pass<T, kC>(P, ntiles, post == 1, last && has_beta, last ? ar : T(1), last ? ai : T(0), br, bi, stream);
+    const bool dense_in = !(k == d - 1 && xs), dense_out = !(k == 0 && ys);
+    run_pass<T, kC>(P, ntiles, post == 1, dense_in, dense_out, last && has_beta, last ? ar : T(1), last ? ai : T(0),
+                    br, bi, stream);
     in = P.Y;
     which ^= 1;
   }

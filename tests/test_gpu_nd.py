@@ -87,6 +87,9 @@ SHAPES = [
     ([3, 4, 2, 5], [2, 3, 4, 3], "NTTN"),
     ([6, 6, 6, 6], [6, 6, 6, 6], "NNNN"),
     ([2, 3, 2, 2, 3], [3, 2, 2, 3, 2], "TNTNT"),
+    ([8, 32], [5, 32], "TN"),            # a pass with 32 faster elements: two columns per lane
+    ([3, 4, 16], [2, 4, 16], "NTN"),     # 64 faster elements: four columns per lane
+    ([7, 64], [9, 64], "NN"),
 ]
 
 
