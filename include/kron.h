@@ -520,14 +520,18 @@ int kron_copy_bytes(const void* src, void* dst, size_t bytes, hipStream_t stream
    workgroups per compute unit (0 = as many as can be resident; -1 = back to
    the built-in default) and a kernel `variant`:
      2-D: 0/1/2 = 4/8/2 tiles in flight per wavefront, direct loads;
-          3 = tiles staged through LDS (n != 16).
+          3 = tiles staged through LDS (n != 16); 4 = 3 with two LDS slices
+          per wavefront, each span's stores issued after the next span's
+          prefetched operands are in LDS (n != 16; otherwise variant 0).
      3-D: 0 plain; 1 next tile prefetched; 2 contiguous 1 KiB rows (a second
           register exchange); 3 = 1 + 2; 4/5 = contiguous rows with a window
           of 2/4 slab loads in flight; 6/7 = 4/5 with the next tile's first
           slabs requested early; 8 = tiles staged through LDS (n != 16;
           otherwise variant 0); 9/10 = n = 16,
           contiguous rows, the result stores interleaved with the next
-          tile's slab loads (window 2/4; otherwise variant 4).  The paper
+          tile's slab loads (window 2/4; otherwise variant 4); 11 = 8 with
+          the stores deferred as in 2-D variant 4 (n != 16; otherwise
+          variant 0).  The paper
    picks its kernel method by matrix size and fixes the number of thread
    blocks (Sections 4 and 5); here the choice is a per-(mode, dim, n) table
    that an autotuner can fill.  Process-wide, not thread-safe against

@@ -81,7 +81,7 @@ int set_launch_shape(int mode, int dim, int n, int blocks_per_cu, int variant) {
   if (dim < 2 || dim > 3) return -2;
   if (n < 1 || n > 16) return -3;
   if (blocks_per_cu < -1 || blocks_per_cu > 64) return -4;
-  if (variant < 0 || variant > (dim == 3 ? 10 : 3)) return -5;
+  if (variant < 0 || variant > (dim == 3 ? 11 : 4)) return -5;
   g_shape[mode][dim - 2][n].store(blocks_per_cu < 0 ? -1 : blocks_per_cu * 16 + variant, std::memory_order_relaxed);
   return 0;
 }
@@ -689,10 +689,17 @@ int kron_autotune(int mode, int dim, int n, const void* A, const void* B, const 
     if (e0) (void)hipEventDestroy(e0);
     return (int)e;
   }
-  // candidate variants: 2-D 0-3; 3-D 0-7 plus 9-10 (n = 16) or 8 (other n)
-  int vars[11], nvar = 0;
-  for (int v = 0; v <= (dim == 3 ? 10 : 3); ++v)
-    if (dim == 2 || (v == 8 ? n != 16 : v < 8 || n == 16)) vars[nvar++] = v;
+  // candidate variants: 2-D 0-3 plus 4 (n != 16); 3-D 0-7 plus 9-10
+  // (n = 16) or 8 and 11 (other n)
+  int vars[12], nvar = 0;
+  for (int v = 0; v <= (dim == 3 ? 11 : 4); ++v) {
+    bool use;
+    if (dim == 2) use = v < 4 || n != 16;
+    else if (v == 8 || v == 11) use = n != 16;
+    else if (v == 9 || v == 10) use = n == 16;
+    else use = true;
+    if (use) vars[nvar++] = v;
+  }
   const int blocks[] = {0, 1, 2, 3, 4};
   constexpr int kNB = sizeof(blocks) / sizeof(blocks[0]);
   // Every shape is timed in three sweeps (forward, reverse, forward) and

@@ -139,14 +139,15 @@ __device__ __attribute__((noinline)) int64_t run_group_2d(const GroupDesc& gd, i
     // the next unit of the chunk is loaded into registers while the current
     // one is computed and written out (as in the single-group kernel)
     RunPrefetch<io_t, kT * S::kElems> pf;
+    Pending<io_t> po;  // one slice per wavefront: results are written out at once
     do {
       const unsigned long long nx = cl.issue();
       int64_t u = ct.first(c) - u0;
       const int64_t ue = ct.first(c + 1) - u0;
       if (u < ue) pf.issue(X + u * kT * S::kElems, span_elems<S>(u * kT, ntiles, gd.count), lane);
       for (; u < ue; ++u)
-        staged2d_tiles<S, true>(st, slice, X, Y, u * kT, ntiles, gd.count, lane, &pf,
-                                u + 1 < ue ? (u + 1) * kT : ntiles);
+        staged2d_step<false>(st, slice, X, Y, u * kT, ntiles, gd.count, lane, pf, po,
+                             u + 1 < ue ? (u + 1) * kT : ntiles);
       c = Claim::value(nx);
     } while (c < ct.nchunks && ct.first(c) < u1);
   } else {
@@ -199,6 +200,7 @@ __device__ __attribute__((noinline)) int64_t run_group_3d(const GroupDesc& gd, i
     // one is computed (up to 8 vectors per lane; larger tiles copy the rest
     // when they are committed)
     RunPrefetch<io_t, S::kElems> pf;
+    Pending<io_t> po;  // one slice per wavefront: results are written out at once
     auto ops_of = [&](int64_t t) { return (int)((gd.count - t * S::kOps) < S::kOps ? gd.count - t * S::kOps : S::kOps); };
     do {
       const unsigned long long nx = cl.issue();
@@ -206,8 +208,9 @@ __device__ __attribute__((noinline)) int64_t run_group_3d(const GroupDesc& gd, i
       const int64_t te = ct.first(c + 1) - u0;
       if (t < te) pf.issue(X + t * S::kElems, ops_of(t) * S::E, lane);
       for (; t < te; ++t)
-        staged3d_tile<S, true>(st, slice, X + t * S::kElems, Y + t * S::kElems, gd.count - t * S::kOps, lane, &pf,
-                               t + 1 < te ? X + (t + 1) * S::kElems : nullptr, gd.count - (t + 1) * S::kOps);
+        staged3d_step<false>(st, slice, X + t * S::kElems, Y + t * S::kElems,
+                             gd.count - t * S::kOps, lane, pf, po, t + 1 < te ? X + (t + 1) * S::kElems : nullptr,
+                             gd.count - (t + 1) * S::kOps);
       c = Claim::value(nx);
     } while (c < ct.nchunks && ct.first(c) < u1);
   } else {

@@ -313,12 +313,63 @@ struct Tile3D {
     }
   }
 
+  // Position in t of the stage-3 result for output slab o while it is still
+  // in the exchanged arrangement: output o = drow(g, r) is computed from the
+  // four slabs 4g .. 4g + 3 alone, so it can be written back into slab 4g + r
+  // of that same group (the identity for FP32, where drow(g, r) = 4g + r).
+  __device__ static constexpr int home(int o) {
+    int h = 0;
+    for (int gg = 0; gg < 4; ++gg)
+      for (int rr = 0; rr < 4; ++rr)
+        if (M::drow(gg, rr) == o) h = 4 * gg + rr;
+    return h;
+  }
+
   // The third mode needs every slab: exchange lane groups and slabs, contract,
   // and (kContig) exchange back so that the result is stored in 1 KiB rows.
   __device__ __forceinline__ void stage3(acc_t (&t)[16]) const {
     exchange_groups_slabs(t);
-    acc_t u[16];
-    if constexpr (kContig) {
+    if constexpr (kContig && Q == 1) {
+      // In place, one group of four slabs at a time (a 4-slab copy instead of
+      // a second 16-slab array): the results of group g go to t[4g + r].
+      // Packed tiles (Q > 1) keep the two-array form below, which the
+      // compiler schedules with fewer spills there.
+#pragma unroll
+      for (int gg = 0; gg < 4; ++gg) {
+        acc_t src[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) src[s] = t[4 * gg + s];
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+          const int k = M::drow(gg, rr);
+          if (!live(k)) {
+            t[4 * gg + rr] = acc_t{0, 0, 0, 0};
+            continue;
+          }
+          acc_t z;
+#pragma unroll
+          for (int s = 0; s < 4; ++s) z[s] = src[s][rr];
+          t[4 * gg + rr] = M::template db<kS>(fA, z);  // contract a: rows i, column j, slab k
+        }
+      }
+      exchange_groups_slabs_at<home>(t);  // -> slab i, slots k on (g, s), still at home(k)
+      // slab i = drow(g, r) takes element r of the results for slabs 4g + s,
+      // which sit at home(4g + s): both sets are the same four registers
+#pragma unroll
+      for (int gg = 0; gg < 4; ++gg) {
+        acc_t src[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) src[s] = t[home(4 * gg + s)];
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+          acc_t z;
+#pragma unroll
+          for (int s = 0; s < 4; ++s) z[s] = src[s][rr];
+          t[M::drow(gg, rr)] = z;
+        }
+      }
+    } else if constexpr (kContig) {
+      acc_t u[16];
 #pragma unroll
       for (int k = 0; k < 16; ++k) {
         if (!live(k)) {
@@ -329,10 +380,11 @@ struct Tile3D {
         regather(t, k, z);
         u[k] = M::template db<kS>(fA, z);  // contract a: rows i, column j, slab k
       }
-      exchange_groups_slabs(u);       // -> slab i, slots k on (g, s)
+      exchange_groups_slabs(u);  // -> slab i, slots k on (g, s)
 #pragma unroll
       for (int i = 0; i < 16; ++i) regather(u, i, t[i]);
     } else {
+      acc_t u[16];
 #pragma unroll
       for (int i = 0; i < 16; ++i) {
         if (!live(i)) {
@@ -446,8 +498,18 @@ __global__ __launch_bounds__(kBlock) void kron2d_kernel(const typename M::io_t* 
 //            and stages 1-2 run on each slab as it lands (scheduling barriers
 //            keep the compiler from hoisting every load to the top).  Fewer
 //            bytes in flight per wavefront keep HBM queues short.
+// FP64 tiles hold twice the registers of FP32 ones; without a hint the
+// compiler spends them all and one wavefront runs per SIMD, which leaves the
+// slab loads of a single wavefront to cover HBM latency.  Two per SIMD fit
+// without spilling once stage 3 runs in place, for n = 16 (packed and padded
+// tiles carry more per-lane addressing and would spill).
+template <class M, int N>
+constexpr int kernel3d_waves() {
+  return sizeof(typename M::io_t) == 8 && N == 16 ? 2 : 1;
+}
+
 template <class M, int N, bool kVec, bool kTrans, bool kPipe, bool kContig, int kWindow>
-__global__ __launch_bounds__(kBlock) void kron3d_kernel(const typename M::io_t* __restrict__ A,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kernel3d_waves<M, N>()))) void kron3d_kernel(const typename M::io_t* __restrict__ A,
                                                         const typename M::io_t* __restrict__ B,
                                                         const typename M::io_t* __restrict__ C,
                                                         const typename M::io_t* __restrict__ X,
@@ -583,11 +645,12 @@ __global__ __launch_bounds__(kBlock) void kron_ex_kernel(const typename M::io_t*
 // slab of its next tile and requests the slab kWindow further on.  Reads and
 // writes then alternate per 1 KiB row instead of a whole tile of each in a
 // burst; contiguous-row stage order, so every access is one 1 KiB row.
-// Two 16-slab tiles live at once: with 4-byte elements they fit three
-// wavefronts per SIMD without spilling when the compiler is held to that.
+// At most 16 + kWindow slabs are live at once (a result slab dies as it is
+// stored): with 4-byte elements that fits three wavefronts per SIMD, with
+// 8-byte ones two (stage 3 in place).
 template <class M>
 constexpr int stream_waves() {
-  return sizeof(typename M::io_t) == 8 ? 1 : 3;
+  return sizeof(typename M::io_t) == 8 ? 2 : 3;
 }
 
 template <class M, bool kTrans, int kWindow>

@@ -76,7 +76,9 @@ template <class M, int N, int Dim>
 constexpr bool kStageable = N != 16;
 
 // 2-D variants: tiles kept in flight per wavefront, 0 -> 4, 1 -> 8, 2 -> 2;
-// 3 -> tiles staged through LDS (n != 16).
+// 3 -> tiles staged through LDS (n != 16), 4 -> the same with two LDS slices
+// per wavefront and each span's copy-out issued after the next span's
+// operands are committed (n = 16 runs variant 0).
 template <class M, int N, bool kTrans>
 int launch2d_n(const typename M::io_t* A, const typename M::io_t* B, const typename M::io_t* X,
                typename M::io_t* Y, int64_t batch, hipStream_t stream, int mode) {
@@ -85,8 +87,8 @@ int launch2d_n(const typename M::io_t* A, const typename M::io_t* B, const typen
   const int64_t ntiles = (batch + ops - 1) / ops;
   const LaunchShape sh = launch_shape(mode, 2, N);
   if constexpr (kStageable<M, N, 2>) {
-    if (sh.variant == 3) {
-      auto k = kron2d_staged_kernel<M, N, kTrans>;
+    if (sh.variant == 3 || sh.variant == 4) {
+      auto k = sh.variant == 4 ? kron2d_staged_kernel<M, N, kTrans, true> : kron2d_staged_kernel<M, N, kTrans, false>;
       constexpr int kT = Staged2D<M, N, kTrans>::kT;
       const int64_t waves = (ntiles + kT - 1) / kT;
       hipLaunchKernelGGL(k, dim3(grid_blocks(waves, occupancy_blocks(k), sh.blocks_per_cu)), dim3(kBlock), 0,
@@ -161,7 +163,9 @@ void launch3d_v(int variant, const typename M::io_t* A, const typename M::io_t* 
 // 6/7 = 4/5 with the next tile's first slabs requested before stage 3,
 // 8 = tiles staged through LDS (n != 16; n = 16 falls back to variant 0), 9/10 = n = 16 with the result stores
 // interleaved with the next tile's loads and stages 1-2, window 2/4 (other
-// sizes and unaligned arrays run variant 4, the same stage order).
+// sizes and unaligned arrays run variant 4, the same stage order), 11 = 8
+// with two LDS slices per wavefront where they fit and each tile's copy-out
+// issued after the next tile's operands are committed (n = 16: variant 0).
 template <class M, int N, bool kTrans>
 int launch3d_n(const typename M::io_t* A, const typename M::io_t* B, const typename M::io_t* C,
                const typename M::io_t* X, typename M::io_t* Y, int64_t batch, hipStream_t stream, int mode) {
@@ -170,8 +174,8 @@ int launch3d_n(const typename M::io_t* A, const typename M::io_t* B, const typen
   const int64_t ntiles = (batch + ops - 1) / ops;
   const LaunchShape sh = launch_shape(mode, 3, N);
   if constexpr (kStageable<M, N, 3>) {
-    if (sh.variant == 8) {
-      auto k = kron3d_staged_kernel<M, N, kTrans>;
+    if (sh.variant == 8 || sh.variant == 11) {
+      auto k = sh.variant == 11 ? kron3d_staged_kernel<M, N, kTrans, true> : kron3d_staged_kernel<M, N, kTrans, false>;
       hipLaunchKernelGGL(k, dim3(grid_blocks(ntiles, occupancy_blocks(k), sh.blocks_per_cu)), dim3(kBlock), 0,
                          stream, A, B, C, X, Y, batch, ntiles);
       return 0;

@@ -259,17 +259,44 @@ struct RunPrefetch {
   }
 };
 
+// Results of a tile (or span) left in an LDS slice, copied out later.  With
+// two slices per wavefront the copy-out of tile t is issued after tile
+// t + 1's prefetched operands are committed to the other slice: the commit
+// waits for those loads, and one counter covers both loads and stores here,
+// so stores issued just before it would be waited for as well.  Issued after
+// it, they complete while tile t + 1 is computed.
+template <typename io_t>
+struct Pending {
+  io_t* dst = nullptr;
+  const io_t* src = nullptr;
+  int count = 0;
+
+  __device__ __forceinline__ void hold(io_t* dst_, const io_t* src_, int count_) {
+    dst = dst_;
+    src = src_;
+    count = count_;
+  }
+  __device__ __forceinline__ void write(int lane) {
+    if (count > 0) copy_out(dst, src, count, lane);
+    count = 0;
+  }
+};
+
+// Two slices per wavefront when both fit in LDS at four wavefronts per SIMD
+// (16 per CU, 160 KiB of LDS), one otherwise.
+template <int kSliceBytes>
+constexpr int stage_buffers() {
+  return 2 * kSliceBytes * 16 <= 160 * 1024 ? 2 : 1;
+}
+
 // One tile through an LDS slice of S::kSlice elements (16-byte aligned).
 // Packed tiles (several operands) whose result holds a non-finite value are
 // redone one operand at a time: the slice is zeroed, only operand o is copied
 // in (at its own place), the same code runs, and only operand o is copied
-// out, so IEEE propagation stays inside operand o.  With kPf the tile's
-// operands come from the prefetch `pf` (issued earlier), and the prefetch of
-// the next tile (Xnext, if not null) is issued once this one sits in LDS.
-template <class S, bool kPf = false, class P = RunPrefetch<typename S::io_t, 1>>
+// out, so IEEE propagation stays inside operand o.
+template <class S>
 __device__ __forceinline__ void staged3d_tile(const S& st, typename S::io_t* slice, const typename S::io_t* Xt,
-                                              typename S::io_t* Yt, int64_t rem, int l, P* pf = nullptr,
-                                              const typename S::io_t* Xnext = nullptr, int64_t rem_next = 0) {
+                                              typename S::io_t* Yt, int64_t rem, int l) {
   using acc_t = typename S::acc_t;
   typename S::io_t* lds = stage_base(slice, Xt);
   const int nops = (int)(rem < S::kOps ? rem : S::kOps);
@@ -280,16 +307,9 @@ __device__ __forceinline__ void staged3d_tile(const S& st, typename S::io_t* sli
     wave_sync_lds();  // the previous copy-out has read the slice
     if (o >= 0) zero_fill(lds, 0, S::kElems, l);
     else zero_fill(lds, count, S::kElems, l);
-    if (kPf && o < 0) {
-      pf->commit(lds, l);
-    } else {
-      wave_sync_lds();
-      copy_in(Xt + first, lds + first, count, l);
-    }
     wave_sync_lds();
-    if constexpr (kPf) {
-      if (o < 0 && Xnext) pf->issue(Xnext, (int)(rem_next < S::kOps ? rem_next : S::kOps) * S::E, l);
-    }
+    copy_in(Xt + first, lds + first, count, l);
+    wave_sync_lds();
     acc_t v[16];
 #pragma unroll
     for (int a = 0; a < 16; ++a) {
@@ -317,6 +337,68 @@ __device__ __forceinline__ void staged3d_tile(const S& st, typename S::io_t* sli
   }
 }
 
+// One tile of a prefetched sequence: its prefetched operands are committed
+// to `slice`, then (kDefer) the previous tile's results, left in the
+// wavefront's other slice, are copied out, the next tile's operands
+// requested, this tile computed, and its results left in `slice` and held in
+// `po`.  Without kDefer (one slice) the results are copied out at once.  A
+// packed tile with a non-finite result is redone one operand at a time as
+// in staged3d_tile, each operand written out at once.
+template <bool kDefer, class S, class P>
+__device__ __forceinline__ void staged3d_step(const S& st, typename S::io_t* slice, const typename S::io_t* Xt,
+                                              typename S::io_t* Yt, int64_t rem, int l, P& pf,
+                                              Pending<typename S::io_t>& po, const typename S::io_t* Xnext,
+                                              int64_t rem_next) {
+  using acc_t = typename S::acc_t;
+  typename S::io_t* lds = stage_base(slice, Xt);
+  const int nops = (int)(rem < S::kOps ? rem : S::kOps);
+  for (int o = -1;;) {
+    // o < 0: the whole tile; o >= 0: operand o alone
+    const int first = o < 0 ? 0 : o * S::E;
+    const int count = o < 0 ? nops * S::E : S::E;
+    wave_sync_lds();  // this slice's last copy-out has read it
+    if (o >= 0) zero_fill(lds, 0, S::kElems, l);
+    else zero_fill(lds, count, S::kElems, l);
+    if (o < 0) {
+      pf.commit(lds, l);
+      if constexpr (kDefer) po.write(l);
+    } else {
+      wave_sync_lds();
+      copy_in(Xt + first, lds + first, count, l);
+    }
+    wave_sync_lds();
+    if (o < 0 && Xnext) pf.issue(Xnext, (int)(rem_next < S::kOps ? rem_next : S::kOps) * S::E, l);
+    acc_t v[16];
+#pragma unroll
+    for (int a = 0; a < 16; ++a) {
+      v[a] = st.read(lds, a);
+      if (S::Tile::live(a)) st.tile.stage12(v[a]);
+    }
+    st.tile.stage3(v);
+    if constexpr (S::kOps > 1) {
+      if (o < 0) {
+        bool fin = true;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) fin = fin && all_finite(v[i]);
+        if (__any(!fin)) {
+          o = 0;
+          continue;
+        }
+      }
+    }
+    wave_sync_lds();  // every lane has read its slots
+#pragma unroll
+    for (int i = 0; i < 16; ++i) st.write(lds, i, v[i]);
+    if (kDefer && o < 0) {
+      po.hold(Yt, lds, count);
+      break;
+    }
+    wave_sync_lds();
+    copy_out(Yt + first, lds + first, count, l);
+    if (o < 0 || ++o >= nops) break;
+  }
+}
+
 // Waves per SIMD the 3-D staged kernel is held to: single-operand tiles for
 // n = 9 .. 13 fit four (their LDS slices are small); the larger tiles are
 // limited by LDS to two anyway and are left unconstrained (1).
@@ -325,7 +407,12 @@ constexpr int staged3d_waves() {
   return N >= 9 && N <= 13 ? 4 : 1;
 }
 
-template <class M, int N, bool kTrans>
+// kDefer selects the prefetch pipeline of staged3d_step: two slices per
+// wavefront with each tile's copy-out issued after the next tile's commit,
+// and one wait for the factor loads before the loop (launch variant 11);
+// otherwise one slice, results written out as soon as they are in it
+// (variant 8).  Which is faster depends on the size; the launch table picks.
+template <class M, int N, bool kTrans, bool kDefer>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(staged3d_waves<N>()))) void kron3d_staged_kernel(const typename M::io_t* __restrict__ A,
                                                                const typename M::io_t* __restrict__ B,
                                                                const typename M::io_t* __restrict__ C,
@@ -334,28 +421,35 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(staged3d
                                                                int64_t ntiles) {
   using S = Staged3D<M, N, kTrans>;
   using io_t = typename M::io_t;
-  __shared__ __attribute__((aligned(16))) io_t slices[kBlock / kWave][S::kSlice];
+  using P = RunPrefetch<io_t, S::kElems>;
+  // small tiles: the next tile's operands (at most 4 vectors per lane) are
+  // loaded while the current one is computed; larger tiles would give up
+  // occupancy for the registers
+  constexpr bool kPf = P::kAll <= 4;
+  constexpr int kBuf = kPf && kDefer ? stage_buffers<S::kSlice * (int)sizeof(io_t)>() : 1;
+  __shared__ __attribute__((aligned(16))) io_t slices[kBlock / kWave][kBuf][S::kSlice];
   const int l = threadIdx.x & 63, L = l & 15, g = l >> 4;
-  io_t* lds = slices[threadIdx.x >> 6];
+  const int w = threadIdx.x >> 6;
   const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * kBlock) >> 6;
   const S st(A, B, C, L, g);
-  using P = RunPrefetch<io_t, S::kElems>;
-  if constexpr (P::kAll <= 4) {
-    // small tiles: the next tile's operands (at most 4 vectors per lane) are
-    // loaded while the current one is computed; larger tiles would give up
-    // occupancy for the registers
+  if constexpr (kDefer) wait_loads();
+  if constexpr (kPf) {
     P pf;
+    Pending<io_t> po;
     int64_t t = wave;
+    int b = 0;
     if (t < ntiles) pf.issue(X + t * S::kElems, (int)((batch - t * S::kOps) < S::kOps ? batch - t * S::kOps : S::kOps) * S::E, l);
-    for (; t < ntiles; t += nwaves) {
+    for (; t < ntiles; t += nwaves, b ^= kBuf - 1) {
       const int64_t tn = t + nwaves;
-      staged3d_tile<S, true>(st, lds, X + t * S::kElems, Y + t * S::kElems, batch - t * S::kOps, l, &pf,
-                             tn < ntiles ? X + tn * S::kElems : nullptr, batch - tn * S::kOps);
+      staged3d_step<kBuf == 2>(st, slices[w][b], X + t * S::kElems, Y + t * S::kElems, batch - t * S::kOps, l, pf, po,
+                               tn < ntiles ? X + tn * S::kElems : nullptr, batch - tn * S::kOps);
     }
+    wave_sync_lds();
+    po.write(l);
   } else {
     for (int64_t t = wave; t < ntiles; t += nwaves)
-      staged3d_tile(st, lds, X + t * S::kElems, Y + t * S::kElems, batch - t * S::kOps, l);
+      staged3d_tile(st, slices[w][0], X + t * S::kElems, Y + t * S::kElems, batch - t * S::kOps, l);
   }
 }
 
@@ -402,12 +496,11 @@ struct Staged2D {
   }
 };
 
-// kT consecutive tiles (from tile t0; those at or past `last` hold nothing)
-// through one LDS span: the run of operands they hold is copied in as one
-// piece, the tail of the span zero-filled, and the results copied out as one
-// piece.  A packed tile with a non-finite result is redone per operand as in
-// 3-D; its span part is then left out of the copy-out.
-// Operands in the span of tiles t0 .. min(t0 + kT, last) - 1.
+// A span is kT consecutive tiles (from tile t0; those at or past `last` hold
+// nothing) that move through the wavefront's LDS as one piece: the run of
+// operands they hold is copied in as one piece, the tail of the span
+// zero-filled, and the results copied out as one piece.
+// Elements of the operands in the span of tiles t0 .. min(t0 + kT, last) - 1.
 template <class S>
 __device__ __forceinline__ int span_elems(int64_t t0, int64_t last, int64_t batch) {
   const int64_t ops_left = batch - t0 * S::kOps;
@@ -416,48 +509,15 @@ __device__ __forceinline__ int span_elems(int64_t t0, int64_t last, int64_t batc
   return (int)(ops_left < cap ? ops_left : cap) * S::E;
 }
 
-// With kPf the span's operands come from the prefetch `pf`, and the next
-// span (tile tn, if tn < last) is prefetched once this one sits in LDS.
-template <class S, bool kPf = false, class P = RunPrefetch<typename S::io_t, 1>>
-__device__ __forceinline__ void staged2d_tiles(const S& st, typename S::io_t* span, const typename S::io_t* X,
-                                               typename S::io_t* Y, int64_t t0, int64_t last, int64_t batch,
-                                               int l, P* pf = nullptr, int64_t tn = 0) {
+// The fallback of a span with a non-finite packed tile (results of the
+// other tiles already in the span): every tile is written out at once, the
+// bad ones recomputed operand by operand.
+template <class S>
+__device__ __forceinline__ void staged2d_redo(const S& st, typename S::io_t* span, const typename S::io_t* Xs,
+                                              typename S::io_t* Ys, int nops_all, const bool (&bad)[S::kT], int l) {
   using io_t = typename S::io_t;
   using acc_t = typename S::acc_t;
   constexpr int kT = S::kT;
-  const int count = span_elems<S>(t0, last, batch);
-  const int nops_all = count / S::E;
-  const io_t* Xs = X + t0 * S::kElems;
-  io_t* Ys = Y + t0 * S::kElems;
-  span = stage_base(span, Xs);
-  wave_sync_lds();
-  zero_fill(span, count, kT * S::kElems, l);
-  if constexpr (kPf) pf->commit(span, l);
-  else copy_in(Xs, span, count, l);
-  wave_sync_lds();
-  if constexpr (kPf) {
-    if (tn < last) pf->issue(X + tn * S::kElems, span_elems<S>(tn, last, batch), l);
-  }
-  acc_t v[kT];
-#pragma unroll
-  for (int j = 0; j < kT; ++j) v[j] = st.tile.compute(st.read(span + j * S::kElems));
-  bool bad[kT];
-  bool any_bad = false;
-#pragma unroll
-  for (int j = 0; j < kT; ++j) {
-    const int nops = nops_all - j * S::kOps;
-    bad[j] = S::kOps > 1 && nops > 0 && __any(!all_finite(v[j]));
-    any_bad |= bad[j];
-  }
-  wave_sync_lds();
-#pragma unroll
-  for (int j = 0; j < kT; ++j)
-    if (!bad[j]) st.write(span + j * S::kElems, v[j]);
-  wave_sync_lds();
-  if (!any_bad) {
-    copy_out(Ys, span, count, l);
-    return;
-  }
   if constexpr (S::kOps > 1) {
     for (int j = 0; j < kT; ++j) {
       const int nops = nops_all - j * S::kOps;
@@ -487,7 +547,54 @@ __device__ __forceinline__ void staged2d_tiles(const S& st, typename S::io_t* sp
   }
 }
 
-template <class M, int N, bool kTrans>
+// A span of a prefetched sequence, as staged3d_step (kDefer: two slices per
+// wavefront, the previous span's copy-out issued after this span's commit).
+// A span with a non-finite packed tile is finished by staged2d_redo (every
+// part written out at once, the bad tiles redone per operand as in 3-D).
+template <bool kDefer, class S, class P>
+__device__ __forceinline__ void staged2d_step(const S& st, typename S::io_t* span, const typename S::io_t* X,
+                                              typename S::io_t* Y, int64_t t0, int64_t last, int64_t batch, int l,
+                                              P& pf, Pending<typename S::io_t>& po, int64_t tn) {
+  using io_t = typename S::io_t;
+  using acc_t = typename S::acc_t;
+  constexpr int kT = S::kT;
+  const int count = span_elems<S>(t0, last, batch);
+  const int nops_all = count / S::E;
+  const io_t* Xs = X + t0 * S::kElems;
+  io_t* Ys = Y + t0 * S::kElems;
+  span = stage_base(span, Xs);
+  wave_sync_lds();  // this span's last copy-out has read it
+  zero_fill(span, count, kT * S::kElems, l);
+  pf.commit(span, l);
+  if constexpr (kDefer) po.write(l);
+  wave_sync_lds();
+  if (tn < last) pf.issue(X + tn * S::kElems, span_elems<S>(tn, last, batch), l);
+  acc_t v[kT];
+#pragma unroll
+  for (int j = 0; j < kT; ++j) v[j] = st.tile.compute(st.read(span + j * S::kElems));
+  bool bad[kT];
+  bool any_bad = false;
+#pragma unroll
+  for (int j = 0; j < kT; ++j) {
+    const int nops = nops_all - j * S::kOps;
+    bad[j] = S::kOps > 1 && nops > 0 && __any(!all_finite(v[j]));
+    any_bad |= bad[j];
+  }
+  wave_sync_lds();
+#pragma unroll
+  for (int j = 0; j < kT; ++j)
+    if (!bad[j]) st.write(span + j * S::kElems, v[j]);
+  wave_sync_lds();
+  if (!any_bad) {
+    if constexpr (kDefer) po.hold(Ys, span, count);
+    else copy_out(Ys, span, count, l);
+    return;
+  }
+  staged2d_redo(st, span, Xs, Ys, nops_all, bad, l);
+}
+
+// kDefer as for the 3-D kernel (launch variant 4; variant 3 without).
+template <class M, int N, bool kTrans, bool kDefer>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void kron2d_staged_kernel(const typename M::io_t* __restrict__ A,
                                                                const typename M::io_t* __restrict__ B,
                                                                const typename M::io_t* __restrict__ X,
@@ -496,19 +603,25 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
   using S = Staged2D<M, N, kTrans>;
   using io_t = typename M::io_t;
   constexpr int kT = S::kT;
-  __shared__ __attribute__((aligned(16))) io_t slices[kBlock / kWave][S::kSpan];
+  constexpr int kBuf = kDefer ? stage_buffers<S::kSpan * (int)sizeof(io_t)>() : 1;
+  __shared__ __attribute__((aligned(16))) io_t slices[kBlock / kWave][kBuf][S::kSpan];
   const int l = threadIdx.x & 63, L = l & 15, g = l >> 4;
-  io_t* mine = slices[threadIdx.x >> 6];
+  const int w = threadIdx.x >> 6;
   const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * kBlock) >> 6;
   const S st(A, B, L, g);
+  if constexpr (kDefer) wait_loads();
   // the next span's operands (at most about 4 KiB) are loaded while the
-  // current span is computed and written out
+  // current span is computed
   RunPrefetch<io_t, kT * S::kElems> pf;
+  Pending<io_t> po;
   int64_t base = wave * kT;
+  int b = 0;
   if (base < ntiles) pf.issue(X + base * S::kElems, span_elems<S>(base, ntiles, batch), l);
-  for (; base < ntiles; base += nwaves * kT)
-    staged2d_tiles<S, true>(st, mine, X, Y, base, ntiles, batch, l, &pf, base + nwaves * kT);
+  for (; base < ntiles; base += nwaves * kT, b ^= kBuf - 1)
+    staged2d_step<kBuf == 2>(st, slices[w][b], X, Y, base, ntiles, batch, l, pf, po, base + nwaves * kT);
+  wave_sync_lds();
+  po.write(l);
 }
 
 }  // namespace kron

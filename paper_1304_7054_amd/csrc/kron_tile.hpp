@@ -404,6 +404,13 @@ struct ModeBF16 {
   }
 };
 
+// Waits until every vector-memory load of the wavefront has returned
+// (s_waitcnt vmcnt(0)).  Called once after a kernel's factor loads: in a loop
+// that requests the next tile's data ahead of the current tile's arithmetic,
+// the first use of a factor register could otherwise be compiled as a full
+// wait, which also waits for those requests in every iteration.
+__device__ __forceinline__ void wait_loads() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
 // ---- lane-group <-> slab exchange (3-D) --------------------------------------------
 //
 // Before: lane group g, register (slab b, r) holds the element with row index
@@ -454,6 +461,31 @@ __device__ __forceinline__ void transpose_groups_regs(V& v) {
   v[1] = b;
   v[2] = c;
   v[3] = d;
+}
+
+// The same exchange on an array whose logical slab b sits at t[H(b)].
+template <int (*H)(int), typename V>
+__device__ __forceinline__ void exchange_groups_slabs_at(V (&t)[16]) {
+#pragma unroll
+  for (int b = 0; b < 8; ++b)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      auto x = t[H(b)][r], y = t[H(b + 8)][r];
+      swap32(x, y);
+      t[H(b)][r] = x;
+      t[H(b + 8)][r] = y;
+    }
+#pragma unroll
+  for (int b = 0; b < 16; ++b) {
+    if (b & 4) continue;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      auto x = t[H(b)][r], y = t[H(b + 4)][r];
+      swap16(x, y);
+      t[H(b)][r] = x;
+      t[H(b + 4)][r] = y;
+    }
+  }
 }
 
 template <typename V>

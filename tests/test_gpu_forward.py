@@ -248,7 +248,7 @@ def test_repeated_runs_are_bitwise_identical():
     assert np.array_equal(a, b)
 
 
-@pytest.mark.parametrize("n", [4, 7, 16])
+@pytest.mark.parametrize("n", [4, 7, 10, 16])
 @pytest.mark.parametrize("dim", [2, 3])
 @pytest.mark.parametrize("mode", ["f32", "bf16x3", "f64", "bf16", "bf16x6"])
 def test_launch_variants_agree(mode, dim, n):
@@ -269,17 +269,17 @@ def test_launch_variants_agree(mode, dim, n):
     want = _oracle(dim, n, gu.rounded_inputs(mode, mats), gu.rounded_inputs(mode, [X])[0], batch)
     refs = {}
     try:
-        for variant in (list(range(11)) if dim == 3 else [0, 1, 2, 3]):
-            # 3-D variants 2..7, 8 (LDS-staged) and 9/10 (stores interleaved
-            # with the next tile, n = 16; variant 4 otherwise) contract C, B,
-            # A; 0 and 1 contract C, A, B.  Variant 8 at a size it cannot
-            # use runs variant 0.
+        for variant in (list(range(12)) if dim == 3 else [0, 1, 2, 3, 4]):
+            # 3-D variants 2..7, 8 and 11 (LDS-staged) and 9/10 (stores
+            # interleaved with the next tile, n = 16; variant 4 otherwise)
+            # contract C, B, A; 0 and 1 contract C, A, B.  Variants 8 and 11
+            # at a size they cannot use run variant 0.
             stageable = n != 16
             if dim == 2:
                 order = 0
-            elif variant == 8:
+            elif variant in (8, 11):
                 order = 1 if stageable else 0
-            elif variant >= 9:
+            elif variant in (9, 10):
                 order = 1
             else:
                 order = 1 if variant >= 2 else 0

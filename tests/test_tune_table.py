@@ -14,7 +14,7 @@ def test_set_get_and_reset():
     assert kron.kron_get_launch(kron.MODE_F32, 3, 7) == (2, 5)
     kron.kron_set_launch(kron.MODE_F32, 3, 7, -1, 0)
     assert kron.kron_get_launch(kron.MODE_F32, 3, 7) == old
-    for bad in ((5, 3, 7, 0, 0), (-1, 3, 7, 0, 0), (0, 4, 7, 0, 0), (0, 3, 17, 0, 0), (0, 3, 7, 65, 0), (0, 3, 7, 0, 11), (0, 2, 7, 0, 4)):
+    for bad in ((5, 3, 7, 0, 0), (-1, 3, 7, 0, 0), (0, 4, 7, 0, 0), (0, 3, 17, 0, 0), (0, 3, 7, 65, 0), (0, 3, 7, 0, 12), (0, 2, 7, 0, 5)):
         with pytest.raises(kron.KronError):
             kron.kron_set_launch(*bad)
 
