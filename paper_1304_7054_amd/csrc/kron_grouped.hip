@@ -4,10 +4,14 @@
 //
 // kron_grouped_prepare writes a small plan into the caller's device
 // workspace: a header, the group descriptors, and for each of two phases
-// (2-D groups, then 3-D groups) the list of its groups with the number of
-// work units before each.  kron_grouped_launch runs the phases as two
-// persistent kernels in stream order: the 2-D kernel keeps small LDS slices
-// and more wavefronts per SIMD, which a 3-D tile of up to 16 KiB per
+// (2-D groups, 3-D groups) the list of its groups with the number of work
+// units before each.  With groups of both dimensions kron_grouped_launch
+// runs both phases in one persistent kernel: some wavefronts start on the
+// 2-D phase, the others on the 3-D phase, and each moves on to the other
+// phase when its first has no work left, so that the 2-D phase's short,
+// latency-bound units overlap the 3-D phase's streaming.  A batch of one
+// dimension runs that phase's own kernel: the 2-D one keeps small LDS
+// slices and more wavefronts per SIMD, which a 3-D tile of up to 16 KiB per
 // wavefront would otherwise deny every group.
 //
 // Inside a phase, the groups' units (a unit is one 3-D tile or a run of 2-D
@@ -69,7 +73,8 @@ struct PhaseDesc {
 
 struct alignas(64) Header {
   uint64_t magic;
-  int32_t ngroups, pad;
+  int32_t ngroups;
+  int32_t split16;  // one launch for both phases: wavefronts with (index mod 16) below this start on the 2-D one
   int64_t groups_off, total_bytes;
   PhaseDesc phase[2];
 };
@@ -259,6 +264,8 @@ __device__ __forceinline__ int64_t run_group(const GroupDesc& gd, int64_t c, con
   return ct.nchunks;
 }
 
+// One phase's chunks, claimed until none are left; then the wavefront
+// counts itself out of the phase (the last one resets the phase's counters).
 template <int Dim>
 __device__ __forceinline__ void grouped_phase(const uint8_t* __restrict__ ws, float* slice) {
   const Header* h = reinterpret_cast<const Header*>(ws);
@@ -304,10 +311,31 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
   grouped_phase<3>(ws, slices[threadIdx.x >> 6]);
 }
 
+// Both phases in one launch: a share of the wavefronts (split16 of every 16)
+// starts on the 2-D phase and the rest on the 3-D phase; each moves to the
+// other phase once its first one has no chunks left.  The 2-D phase's short,
+// latency-bound units then run beside the 3-D phase's streaming instead of
+// after it.
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) void kron_grouped_kernel(
+    const uint8_t* __restrict__ ws) {
+  __shared__ __attribute__((aligned(16))) float slices[kBlock / kWave][kGroupSlice3];
+  const Header* h = reinterpret_cast<const Header*>(ws);
+  const int wave = (int)((blockIdx.x * kBlock + threadIdx.x) >> 6);
+  float* slice = slices[threadIdx.x >> 6];
+  if ((wave & 15) < h->split16) {
+    grouped_phase<2>(ws, slice);
+    grouped_phase<3>(ws, slice);
+  } else {
+    grouped_phase<3>(ws, slice);
+    grouped_phase<2>(ws, slice);
+  }
+}
+
 // ---- host side ------------------------------------------------------------------
 
 struct Plan {
   int blocks[2];  // per phase; 0 = nothing to run
+  int merged;     // > 0: one launch of kron_grouped_kernel with this many blocks
   size_t bytes;
 };
 std::mutex g_plans_mu;
@@ -343,6 +371,11 @@ int grouped_blocks(int dim) {
   static const int occ2 = std::max(1, occupancy_blocks(kron_grouped2d_kernel));
   static const int occ3 = std::max(1, occupancy_blocks(kron_grouped3d_kernel));
   return device_cus() * (dim == 2 ? occ2 : occ3);
+}
+
+int merged_blocks() {
+  static const int occ = std::max(1, occupancy_blocks(kron_grouped_kernel));
+  return device_cus() * occ;
 }
 
 struct Layout {
@@ -448,12 +481,23 @@ struct Phases {
   std::vector<int64_t> ubefore[2], cstart[2];
   int64_t nchunks[2];
   int blocks[2];
+  int merged;   // blocks of the one-launch kernel when both phases have groups, else 0
+  int split16;  // its wavefronts (of every 16) that start on the 2-D phase
 };
 
+// With groups of both dimensions, both phases run in one launch of
+// kron_grouped_kernel (their chunks cut for that launch's wavefronts), half
+// of its wavefronts starting on each phase.  The 2-D phase's units are short
+// and bound by memory latency, so its share of the time exceeds its share of
+// the bytes; on the 500,000-operand mixed batch any start share from 4 to 10
+// of 16 wavefronts gave the same time, 1 to 3 were slower.
 void build_phases(const kron_group_t* g, int ngroups, Phases& p) {
   phase_lists(g, ngroups, p.lists, p.nlist);
+  const bool both = p.nlist[0] > 0 && p.nlist[1] > 0;
+  p.merged = both ? merged_blocks() : 0;
+  p.split16 = both ? 8 : 0;
   for (int ph = 0; ph < 2; ++ph) {
-    p.blocks[ph] = grouped_blocks(ph + 2);
+    p.blocks[ph] = both ? p.merged : grouped_blocks(ph + 2);
     p.nchunks[ph] = cut_chunks(g, p.lists[ph], p.blocks[ph] * (kBlock / kWave), p.ubefore[ph], p.cstart[ph]);
   }
 }
@@ -479,7 +523,8 @@ int grouped_prepare(const kron_group_t* g, int ngroups, void* ws, size_t ws_byte
   h.ngroups = ngroups;
   h.groups_off = (int64_t)lo.groups_off;
   h.total_bytes = (int64_t)lo.total;
-  Plan plan{{0, 0}, lo.total};
+  h.split16 = p.split16;
+  Plan plan{{0, 0}, p.merged, lo.total};
   for (int ph = 0; ph < 2; ++ph) {
     const size_t ng = (size_t)p.nlist[ph];
     h.phase[ph].ngroups = p.nlist[ph];
@@ -523,6 +568,10 @@ int grouped_launch(const void* ws, hipStream_t stream) {
     plan = f->second;
   }
   const uint8_t* w = static_cast<const uint8_t*>(ws);
+  if (plan.merged > 0) {
+    hipLaunchKernelGGL(kron_grouped_kernel, dim3(plan.merged), dim3(kBlock), 0, stream, w);
+    return 0;
+  }
   if (plan.blocks[0] > 0) hipLaunchKernelGGL(kron_grouped2d_kernel, dim3(plan.blocks[0]), dim3(kBlock), 0, stream, w);
   if (plan.blocks[1] > 0) hipLaunchKernelGGL(kron_grouped3d_kernel, dim3(plan.blocks[1]), dim3(kBlock), 0, stream, w);
   return 0;
