@@ -1,7 +1,11 @@
-// A plain streaming copy with the access pattern of the library's kernels
-// (16-byte non-temporal loads and stores, 4 KiB per wavefront step, a
+// A plain streaming copy (16-byte non-temporal loads and stores, a
 // persistent grid): the achievable-bandwidth reference the measurements of
 // the Kronecker kernels are compared with.  It is not part of the action.
+// Its shape is the fastest of a sweep on MI355X (1 GiB, 2 GiB moved): 2 KiB
+// per wavefront step and two workgroups per CU, 5.95 TB/s; 4 KiB per step
+// gave 5.70-5.76 at one to eight workgroups per CU, 8 KiB per step 3.7-5.5,
+// plain (temporal) accesses 1-5 % less, and one contiguous range per
+// wavefront 4.3-5.0.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -16,7 +20,7 @@ typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
 
 __global__ __launch_bounds__(kBlock) void kron_copy_kernel(const u32x4_t* __restrict__ src, u32x4_t* __restrict__ dst,
                                                           int64_t nvec) {
-  constexpr int kU = 4;  // vectors per lane in flight: 4 KiB per wavefront step
+  constexpr int kU = 2;  // vectors per lane in flight: 2 KiB per wavefront step
   const int l = threadIdx.x & 63;
   const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * kBlock) >> 6;
@@ -45,7 +49,7 @@ extern "C" int kron_copy_bytes(const void* src, void* dst, size_t bytes, hipStre
   if (bytes == 0) return 0;
   const int64_t nvec = (int64_t)(bytes / 16);
   auto k = kron::kron_copy_kernel;
-  const int64_t waves = (nvec + 255) / 256;
+  const int64_t waves = (nvec + 127) / 128;
   hipLaunchKernelGGL(k, dim3(kron::grid_blocks(waves, kron::occupancy_blocks(k), 2)), dim3(kron::kBlock), 0, stream,
                      static_cast<const kron::u32x4_t*>(src), static_cast<kron::u32x4_t*>(dst), nvec);
   const hipError_t e = hipGetLastError();
