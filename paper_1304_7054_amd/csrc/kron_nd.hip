@@ -152,13 +152,21 @@ struct NdAcc<double> {
   __device__ static constexpr int drow(int g, int r) { return g + 4 * r; }
 };
 
+// Input reads are non-temporal unless `keep`: a pass whose output index has
+// more than 16 rows reads each input column once per 16-row block, back to
+// back in the same wavefront, and the later reads then hit the L2 cache.
+template <typename T>
+__device__ __forceinline__ T ld1(const T* p, bool keep) {
+  return keep ? *in_global(p) : __builtin_nontemporal_load(in_global(p));
+}
+
 template <typename T, bool kC>
-__device__ __forceinline__ void ld_elem(const T* p, int64_t e, T& re, T& im) {
+__device__ __forceinline__ void ld_elem(const T* p, int64_t e, T& re, T& im, bool keep = false) {
   if constexpr (kC) {
-    re = __builtin_nontemporal_load(in_global(p) + 2 * e);
-    im = __builtin_nontemporal_load(in_global(p) + 2 * e + 1);
+    re = ld1(p + 2 * e, keep);
+    im = ld1(p + 2 * e + 1, keep);
   } else {
-    re = __builtin_nontemporal_load(in_global(p) + e);
+    re = ld1(p + e, keep);
     im = T(0);
   }
 }
@@ -174,14 +182,15 @@ __device__ __forceinline__ void st_elem(T* p, int64_t e, T re, T im) {
 }
 
 // NS consecutive scalars at p (p aligned to min(16, NS * sizeof(T)) bytes),
-// in 16-byte (or, below 16 bytes, NS-scalar) non-temporal vector accesses.
+// in 16-byte (or, below 16 bytes, NS-scalar) vector accesses, non-temporal
+// unless `keep` (as ld_elem).
 template <typename T, int NS>
-__device__ __forceinline__ void ldv(const T* p, T (&o)[NS]) {
+__device__ __forceinline__ void ldv(const T* p, T (&o)[NS], bool keep = false) {
   constexpr int W = (NS * sizeof(T) >= 16) ? 16 / (int)sizeof(T) : NS;
   typedef T V __attribute__((ext_vector_type(W)));
 #pragma unroll
   for (int q = 0; q < NS / W; ++q) {
-    const V v = __builtin_nontemporal_load(in_global(reinterpret_cast<const V*>(p)) + q);
+    const V v = ld1(reinterpret_cast<const V*>(p) + q, keep);
 #pragma unroll
     for (int e = 0; e < W; ++e) o[q * W + e] = v[e];
   }
@@ -236,6 +245,7 @@ __global__ __launch_bounds__(kBlock) void kron_mode_wide_kernel(NdPass P, int64_
   const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * kBlock) >> 6;
   const int nk = (P.n + 15) / 16;
+  const bool keep = P.rows > 1;
   const int64_t post = P.in.mod[0];
   TileWalk w(ntiles, P.rows, P.chunks, wave, nwaves);
   Digits dc;  // digits (v, u) of the tile's first column
@@ -266,7 +276,7 @@ __global__ __launch_bounds__(kBlock) void kron_mode_wide_kernel(NdPass P, int64_
         const int a = 16 * kc + 4 * g + s;
         T x[NS];
         if (colok && a < P.n) {
-          ldv<T, NS>(X + (xb + (int64_t)a * post) * kS, x);
+          ldv<T, NS>(X + (xb + (int64_t)a * post) * kS, x, keep);
         } else {
 #pragma unroll
           for (int q = 0; q < NS; ++q) x[q] = T(0);
@@ -320,6 +330,38 @@ __global__ __launch_bounds__(kBlock) void kron_mode_wide_kernel(NdPass P, int64_
   }
 }
 
+// 4 x 4 transpose inside each quad of lanes (DPP quad permutations): lane
+// 4q + j, register r ends up with what lane 4q + r held in register j.
+template <int kCtrl>
+__device__ __forceinline__ float dpp_move(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), kCtrl, 0xF, 0xF, false));
+}
+template <int kCtrl>
+__device__ __forceinline__ double dpp_move(double x) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, x);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, kCtrl, 0xF, 0xF, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), kCtrl, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+template <typename T>
+__device__ __forceinline__ void quad_transpose(T (&v)[4]) {
+  constexpr int kXor1 = 0xB1;  // quad_perm(1, 0, 3, 2)
+  constexpr int kXor2 = 0x4E;  // quad_perm(2, 3, 0, 1)
+  const int j = threadIdx.x & 3;
+#pragma unroll
+  for (int base = 0; base < 4; base += 2) {
+    const T recv = dpp_move<kXor1>((j & 1) ? v[base] : v[base + 1]);
+    if (j & 1) v[base] = recv;
+    else v[base + 1] = recv;
+  }
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    const T recv = dpp_move<kXor2>((j & 2) ? v[r] : v[r + 2]);
+    if (j & 2) v[r] = recv;
+    else v[r + 2] = recv;
+  }
+}
+
 // kDataA: the data is the MFMA's A operand (post == 1); otherwise B.
 // kBeta: Out <- alpha * product + beta * Out (the last pass); otherwise
 // Out <- alpha * product.
@@ -340,6 +382,11 @@ __global__ __launch_bounds__(kBlock) void kron_mode_kernel(NdPass P, int64_t nti
   const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * kBlock) >> 6;
   const int nk = (P.n + 15) / 16;
+  const bool keep = P.rows > 1;
+  // vector stores of the output (kDataA): the produced index is the fastest,
+  // m and the column stride are multiples of 4, Y is 16-byte aligned
+  const bool vec_out = kDataA && !kC && P.out.along == 1 && P.m % 4 == 0 && P.out.stride[0] % 4 == 0 &&
+                       (reinterpret_cast<uintptr_t>(P.Y) & 15) == 0;
   TileWalk w(ntiles, P.rows, P.chunks, wave, nwaves);
   Digits din, dout;
   if (w.t < w.t1) {
@@ -381,7 +428,7 @@ __global__ __launch_bounds__(kBlock) void kron_mode_kernel(NdPass P, int64_t nti
       for (int j = 0; j < kU; ++j) {
         if constexpr (kVecA) {
           if (colok[j] && 16 * kc + 4 * g < P.n) {
-            ldv<T, 4 * kS>(X + (xb[j] + 16 * kc + 4 * g) * kS, xv[j]);
+            ldv<T, 4 * kS>(X + (xb[j] + 16 * kc + 4 * g) * kS, xv[j], keep);
           } else {
 #pragma unroll
             for (int q = 0; q < 4 * kS; ++q) xv[j][q] = T(0);
@@ -391,7 +438,7 @@ __global__ __launch_bounds__(kBlock) void kron_mode_kernel(NdPass P, int64_t nti
           for (int s = 0; s < 4; ++s) {
             const int a = 16 * kc + 4 * g + s;
             T xr = 0, xi = 0;
-            if (colok[j] && a < P.n) ld_elem<T, kC>(X, xb[j] + (int64_t)a * P.in.along, xr, xi);
+            if (colok[j] && a < P.n) ld_elem<T, kC>(X, xb[j] + (int64_t)a * P.in.along, xr, xi, keep);
             xv[j][s * kS] = xr;
             if constexpr (kC) xv[j][s * kS + 1] = xi;
           }
@@ -425,6 +472,32 @@ __global__ __launch_bounds__(kBlock) void kron_mode_kernel(NdPass P, int64_t nti
         }
       }
     }
+    if constexpr (kDataA && !kC) {
+      // Output index fastest, dense and 16-byte aligned: a quad transpose
+      // gives each lane four consecutive outputs of one column, written as
+      // one vector (instead of four scattered scalars).
+      if (vec_out && fast_out && out0 % 4 == 0) {
+#pragma unroll
+        for (int j = 0; j < kU; ++j) {
+          T o[4];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) o[r] = ar * dr[j][r];
+          quad_transpose(o);
+          const int i0 = 16 * ic + 4 * (L >> 2);
+          const int jc = 16 * j + A::drow(g, L & 3);
+          if (i0 >= P.m || cb + jc >= cend) continue;
+          T* yp = Y + out0 + jc * P.out.stride[0] + i0;
+          if constexpr (kBeta) {
+            T old[4];
+            ldv<T, 4>(yp, old);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) o[r] += br * old[r];
+          }
+          stv<T, 4>(yp, o);
+        }
+        goto next_tile;
+      }
+    }
 #pragma unroll
     for (int j = 0; j < kU; ++j) {
 #pragma unroll
@@ -445,6 +518,7 @@ __global__ __launch_bounds__(kBlock) void kron_mode_kernel(NdPass P, int64_t nti
         st_elem<T, kC>(Y, e, yr, yi);
       }
     }
+  next_tile:
     const int step = w.next(P.rows, P.chunks);
     if (step == 1) {
       din.add(P.in, kCols);
