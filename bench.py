@@ -867,14 +867,14 @@ def summarize_profiles(trace_dir, fetch_dir, write_dir):
 
 PROFILE_COMMANDS = """\
 export TMPDIR=/tmp
-rocprofv3 --kernel-trace --stats -d gpurun_out/prof_trace -o trace --output-format csv -- python bench.py --only-headline --no-cpu --copy-calibration --steps 20 --warmup 3
-rocprofv3 --pmc FETCH_SIZE -d gpurun_out/prof_fetch -o fetch --output-format csv -- python bench.py --only-headline --no-cpu --copy-calibration --device-warm 0 --steps 3 --warmup 1
-rocprofv3 --pmc WRITE_SIZE -d gpurun_out/prof_write -o write --output-format csv -- python bench.py --only-headline --no-cpu --copy-calibration --device-warm 0 --steps 3 --warmup 1
-python bench.py --summarize-profiles gpurun_out/prof_trace gpurun_out/prof_fetch gpurun_out/prof_write
+rocprofv3 --kernel-trace --stats -d gpurun_out/prof_headline_trace -o trace --output-format csv -- python bench.py --only-headline --no-cpu --copy-calibration --steps 20 --warmup 3
+rocprofv3 --pmc FETCH_SIZE -d gpurun_out/prof_headline_fetch -o fetch --output-format csv -- python bench.py --only-headline --no-cpu --copy-calibration --device-warm 0 --steps 3 --warmup 1
+rocprofv3 --pmc WRITE_SIZE -d gpurun_out/prof_headline_write -o write --output-format csv -- python bench.py --only-headline --no-cpu --copy-calibration --device-warm 0 --steps 3 --warmup 1
+python bench.py --summarize-profiles gpurun_out/prof_headline_trace gpurun_out/prof_headline_fetch gpurun_out/prof_headline_write
 """
 
 
-TRACE_COMMAND = ("rocprofv3 --kernel-trace --stats -d gpurun_out/prof_all -o all --output-format csv -- "
+TRACE_COMMAND = ("rocprofv3 --kernel-trace --stats -d gpurun_out/prof_bench_trace -o all --output-format csv -- "
                  "python bench.py --no-cpu --device-warm 0.2 --steps 20")
 
 
@@ -894,7 +894,7 @@ def summarize_trace(trace_dir):
         "```",
         "export TMPDIR=/tmp",
         TRACE_COMMAND,
-        f"python bench.py --summarize-trace gpurun_out/prof_all",
+        f"python bench.py --summarize-trace gpurun_out/prof_bench_trace",
         "```",
         "",
         "| kernel | calls | avg us | min us | max us |",
