@@ -479,11 +479,16 @@ int kron3d_backward_f64(int n, const double* A, const double* B, const double* C
    that requests no factor gradient.  `ws` is caller-owned device memory of at
    least kron_grouped_backward_workspace_size() bytes (each group's partial
    sums in its own slice).  Every descriptor is checked before anything is
-   launched; the groups then run in descriptor order on `stream`, each as
-   kron{2,3}d_backward_{f32,f64} would.  Returns 0; -1 (groups NULL or an
-   invalid descriptor), -2 (ngroups < 1), -3 (ws NULL while needed), -4
-   (ws_bytes too small), or a positive hipError_t.  The result of every group
-   is the single-group call's, bit for bit. */
+   launched; each group then runs as kron{2,3}d_backward_{f32,f64} would.
+   The groups are spread, largest first, over eight streams the library owns
+   (per device, created on the first call, default priority, never freed),
+   which wait for the work already on `stream` and which `stream` waits for
+   afterwards (events); one group, or a device where the streams cannot be
+   created, runs on `stream` itself.  Asynchronous with respect to the host.
+   Returns 0; -1 (groups NULL or an invalid descriptor), -2 (ngroups < 1), -3
+   (ws NULL while needed), -4 (ws_bytes too small), or a positive
+   hipError_t.  The result of every group is the single-group call's, bit for
+   bit. */
 typedef struct kron_group_grad {
   int32_t dim;      /* 2 or 3 */
   int32_t n;        /* 1..16 */
@@ -506,10 +511,11 @@ int kron_grouped_backward(const kron_group_grad_t* groups, int ngroups, void* ws
 
 /* ---- measurement reference ----------------------------------------------------- */
 
-/* Copies `bytes` bytes from src to dst with the memory access pattern of this
-   library's kernels (16-byte non-temporal loads and stores, a persistent
-   grid): the achievable device-memory bandwidth the Kronecker kernels are
-   compared with.  src and dst: 16-byte aligned device pointers that must not
+/* Copies `bytes` bytes from src to dst with 16-byte non-temporal loads and
+   stores on a persistent grid, in the fastest shape of a copy sweep on
+   MI355X (2 KiB per wavefront step, two workgroups per compute unit): the
+   achievable device-memory bandwidth the Kronecker kernels are compared
+   with.  src and dst: 16-byte aligned device pointers that must not
    overlap; bytes: a multiple of 16.  Returns 0, -1 (src), -2 (dst), -3
    (bytes) or a positive hipError_t; asynchronous on `stream`. */
 int kron_copy_bytes(const void* src, void* dst, size_t bytes, hipStream_t stream);

@@ -3,10 +3,12 @@
 // include/kron.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <cstdint>
 #include <cstring>
 #include <mutex>
+#include <vector>
 
 #include "kron.h"
 #include "kron_runtime.hpp"
@@ -472,6 +474,51 @@ size_t kron_grouped_backward_workspace_size(const kron_group_grad_t* groups, int
   return total;
 }
 
+namespace {
+
+// Streams the grouped backward spreads its groups over (per device, created
+// on first use, default priority, never destroyed): one group's kernels are
+// too small to fill the GPU on their own.
+constexpr int kBwdStreams = 8;
+std::mutex g_bwd_mu;
+hipStream_t g_bwd_streams[64][kBwdStreams];
+bool g_bwd_ready[64];
+
+const hipStream_t* bwd_streams() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  std::lock_guard<std::mutex> lk(g_bwd_mu);
+  if (!g_bwd_ready[dev]) {
+    for (int i = 0; i < kBwdStreams; ++i) {
+      if (hipStreamCreateWithFlags(&g_bwd_streams[dev][i], hipStreamNonBlocking) != hipSuccess) {
+        for (int j = 0; j < i; ++j) (void)hipStreamDestroy(g_bwd_streams[dev][j]);
+        return nullptr;
+      }
+    }
+    g_bwd_ready[dev] = true;
+  }
+  return g_bwd_streams[dev];
+}
+
+int grad_group_run(const kron_group_grad_t& d, void* w, size_t b, hipStream_t stream) {
+  if (d.mode == KRON_MODE_F32) {
+    using T = float;
+    if (d.dim == 2)
+      return kron2d_backward_f32(d.n, (const T*)d.A, (const T*)d.B, (const T*)d.X, (const T*)d.dY, (T*)d.dX,
+                                 (T*)d.dA, (T*)d.dB, d.count, w, b, stream);
+    return kron3d_backward_f32(d.n, (const T*)d.A, (const T*)d.B, (const T*)d.C, (const T*)d.X, (const T*)d.dY,
+                               (T*)d.dX, (T*)d.dA, (T*)d.dB, (T*)d.dC, d.count, w, b, stream);
+  }
+  using T = double;
+  if (d.dim == 2)
+    return kron2d_backward_f64(d.n, (const T*)d.A, (const T*)d.B, (const T*)d.X, (const T*)d.dY, (T*)d.dX,
+                               (T*)d.dA, (T*)d.dB, d.count, w, b, stream);
+  return kron3d_backward_f64(d.n, (const T*)d.A, (const T*)d.B, (const T*)d.C, (const T*)d.X, (const T*)d.dY,
+                             (T*)d.dX, (T*)d.dA, (T*)d.dB, (T*)d.dC, d.count, w, b, stream);
+}
+
+}  // namespace
+
 int kron_grouped_backward(const kron_group_grad_t* groups, int ngroups, void* ws, size_t ws_bytes,
                           hipStream_t stream) {
   if (!groups) return -1;
@@ -483,34 +530,76 @@ int kron_grouped_backward(const kron_group_grad_t* groups, int ngroups, void* ws
   }
   if (need > 0 && !ws) return -3;
   if (ws_bytes < need) return -4;
-  uint8_t* at = static_cast<uint8_t*>(ws);
+  // Fork: the worker streams wait for the work already on `stream`; the
+  // groups go to them in turn; join: `stream` waits for every worker.  Each
+  // group's kernels stay in order on one stream, and its result does not
+  // depend on what runs beside it.  Without worker streams (or with one
+  // group) the groups run on `stream` in descriptor order.
+  const hipStream_t* workers = ngroups > 1 ? bwd_streams() : nullptr;
+  hipEvent_t fork = nullptr;
+  if (workers) {
+    if (hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess) {
+      workers = nullptr;
+    } else {
+      hipError_t e = hipEventRecord(fork, stream);
+      for (int w = 0; w < kBwdStreams && e == hipSuccess; ++w) e = hipStreamWaitEvent(workers[w], fork, 0);
+      if (e != hipSuccess) {
+        (void)hipEventDestroy(fork);
+        return (int)e;
+      }
+    }
+  }
+  // Each group's workspace slice, in descriptor order.
+  std::vector<size_t> off(ngroups);
+  {
+    size_t o = 0;
+    for (int i = 0; i < ngroups; ++i) {
+      off[i] = o;
+      o += grad_group_bytes(groups[i]);
+    }
+  }
+  // Largest groups first, each to the stream with the least work so far
+  // (elements read and written, plus a fixed cost per group for its launches).
+  std::vector<int> order(ngroups);
+  std::vector<double> cost(ngroups);
   for (int i = 0; i < ngroups; ++i) {
     const kron_group_grad_t& d = groups[i];
+    const double e = (double)d.count * (d.dim == 3 ? (double)d.n * d.n * d.n : (double)d.n * d.n);
+    cost[i] = 3.0 * e + 2.0e5;
+    order[i] = i;
+  }
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+  double load[kBwdStreams] = {};
+  uint8_t* base = static_cast<uint8_t*>(ws);
+  int rc = 0;
+  for (int k = 0; k < ngroups && rc == 0; ++k) {
+    const int i = order[k];
+    const kron_group_grad_t& d = groups[i];
     const size_t b = grad_group_bytes(d);
-    void* w = b ? at : nullptr;
-    int rc = 0;
-    if (d.mode == KRON_MODE_F32) {
-      using T = float;
-      if (d.dim == 2)
-        rc = kron2d_backward_f32(d.n, (const T*)d.A, (const T*)d.B, (const T*)d.X, (const T*)d.dY, (T*)d.dX,
-                                 (T*)d.dA, (T*)d.dB, d.count, w, b, stream);
-      else
-        rc = kron3d_backward_f32(d.n, (const T*)d.A, (const T*)d.B, (const T*)d.C, (const T*)d.X, (const T*)d.dY,
-                                 (T*)d.dX, (T*)d.dA, (T*)d.dB, (T*)d.dC, d.count, w, b, stream);
-    } else {
-      using T = double;
-      if (d.dim == 2)
-        rc = kron2d_backward_f64(d.n, (const T*)d.A, (const T*)d.B, (const T*)d.X, (const T*)d.dY, (T*)d.dX,
-                                 (T*)d.dA, (T*)d.dB, d.count, w, b, stream);
-      else
-        rc = kron3d_backward_f64(d.n, (const T*)d.A, (const T*)d.B, (const T*)d.C, (const T*)d.X, (const T*)d.dY,
-                                 (T*)d.dX, (T*)d.dA, (T*)d.dB, (T*)d.dC, d.count, w, b, stream);
+    hipStream_t s = stream;
+    if (workers) {
+      int w = 0;
+      for (int j = 1; j < kBwdStreams; ++j)
+        if (load[j] < load[w]) w = j;
+      load[w] += cost[i];
+      s = workers[w];
     }
     // descriptors were checked above, so only a launch failure can end the loop
-    if (rc > 0) return rc;
-    if (rc < 0) return -1;
-    at += b;
+    rc = grad_group_run(d, b ? base + off[i] : nullptr, b, s);
   }
+  if (workers) {
+    for (int w = 0; w < kBwdStreams; ++w) {
+      hipEvent_t done = nullptr;
+      hipError_t e = hipEventCreateWithFlags(&done, hipEventDisableTiming);
+      if (e == hipSuccess) e = hipEventRecord(done, workers[w]);
+      if (e == hipSuccess) e = hipStreamWaitEvent(stream, done, 0);
+      if (done) (void)hipEventDestroy(done);
+      if (e != hipSuccess && rc == 0) rc = (int)e;
+    }
+    (void)hipEventDestroy(fork);
+  }
+  if (rc > 0) return rc;
+  if (rc < 0) return -1;
   return 0;
 }
 
