@@ -273,7 +273,10 @@ __global__ __launch_bounds__(kBlock) void kron_mode_wide_kernel(NdPass P, int64_
     for (int kc = 0; kc < nk; ++kc) {
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
-        const int a = 16 * kc + 4 * g + s;
+        // real data: step s contracts indices 4s .. 4s + 3 of the block, one
+        // per lane group, so a load instruction covers four consecutive rows
+        // (complex data keeps rows 4g + s, measured faster for it)
+        const int a = kC ? 16 * kc + 4 * g + s : 16 * kc + 4 * s + g;
         T x[NS];
         if (colok && a < P.n) {
           ldv<T, NS>(X + (xb + (int64_t)a * post) * kS, x, keep);
@@ -296,9 +299,17 @@ __global__ __launch_bounds__(kBlock) void kron_mode_wide_kernel(NdPass P, int64_
         }
       }
     }
+    // Real results: register r of lane group g becomes row 4r + g, so a
+    // store instruction (one r) writes four consecutive rows.  FP64
+    // accumulators already hold rows g + 4r; FP32 ones (rows 4g + r) trade
+    // lane groups and registers first.  Complex results keep rows drow(g, r).
+    if constexpr (sizeof(T) == 4 && !kC) {
+#pragma unroll
+      for (int j = 0; j < kW; ++j) transpose_groups_regs(dr[j]);
+    }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int i = 16 * ic + A::drow(g, r);
+      const int i = kC ? 16 * ic + A::drow(g, r) : 16 * ic + 4 * r + g;
       if (i >= P.m || !colok) continue;
       T* yp = Y + (yb + (int64_t)i * post) * kS;
       T o[NS];
