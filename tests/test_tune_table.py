@@ -35,3 +35,28 @@ def test_json_round_trip_applies_only_this_device(tmp_path, monkeypatch):
         assert kron.kron_get_launch(kron.MODE_F32, 2, 10) == before
     finally:
         kron.kron_set_launch(kron.MODE_F32, 2, 9, -1, 0)
+
+
+def test_shipped_table_is_complete_and_accepted():
+    """The launch table that ships for MI355X covers every (mode, dim, n) the
+    forward entry points take, once, for one device key, and the library
+    accepts every entry (the variant exists for that dimension)."""
+    import os
+    path = os.path.join(os.path.dirname(tune.__file__), "tuning", "gfx950.json")
+    with open(path) as f:
+        table = json.load(f)
+    keys = [k.split("|") for k in table]
+    assert {"|".join(k[:2]) for k in keys} and len({"|".join(k[:2]) for k in keys}) == 1
+    seen = {(k[2], int(k[3]), int(k[4])) for k in keys}
+    assert seen == {(m, d, n) for m in tune.MODES for d in (2, 3) for n in range(1, 17)}
+    assert len(seen) == len(table)
+    before = {(m, d, n): kron.kron_get_launch(m, d, n)
+              for m in tune.MODES.values() for d in (2, 3) for n in range(1, 17)}
+    try:
+        for k, e in table.items():
+            _, _, mode, dim, n = k.split("|")
+            kron.kron_set_launch(tune.MODES[mode], int(dim), int(n), int(e["blocks_per_cu"]), int(e["variant"]))
+            assert kron.kron_get_launch(tune.MODES[mode], int(dim), int(n)) == (e["blocks_per_cu"], e["variant"])
+    finally:
+        for (m, d, n), (b, v) in before.items():
+            kron.kron_set_launch(m, d, n, b, v)
