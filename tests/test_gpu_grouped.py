@@ -189,3 +189,46 @@ def test_grouped_counters_return_to_zero():
         else:
             for a, b in zip(first, ys):
                 assert torch.equal(a, b), rep
+
+
+@pytest.mark.parametrize("spec", [
+    [(2, 5, 3), (3, 16, 3000), (3, 10, 2000)],        # a tiny 2-D phase beside a large 3-D one
+    [(2, 16, 60000), (2, 3, 20000), (3, 2, 7)],        # a tiny 3-D phase beside a large 2-D one
+    [(2, 1, 1), (3, 1, 1)],                            # one operand per phase
+])
+def test_grouped_one_launch_skewed_phases(spec):
+    """Both phases in one launch when one of them is tiny: every wavefront
+    works through both chunk sequences (half start on each), the results
+    match the oracle, every group equals the single-group entry point bit
+    for bit, and repeated launches leave the counters at zero and give the
+    same bits."""
+    import struct
+    import paper_1304_7054_amd as kron
+    _need_gpu()
+    groups, host = _make_groups(spec, 41)
+    ws = torch.empty(kron.kron_grouped_workspace_size(groups), dtype=torch.uint8, device=DEV)
+    kron.kron_grouped_prepare(groups, ws)
+    first = None
+    for rep in range(3):
+        for g in groups:
+            g["Y"].fill_(float("nan"))
+        kron.kron_grouped_launch(ws)
+        torch.cuda.synchronize()
+        raw = ws.cpu().numpy().tobytes()
+        for ph in range(2):
+            counter_off = struct.unpack_from("<q", raw, 32 + 32 * ph + 24)[0]
+            assert struct.unpack_from("<QI", raw, counter_off) == (0, 0), (rep, ph)
+        ys = [g["Y"].clone() for g in groups]
+        if first is None:
+            _check(groups, host)
+            first = ys
+        else:
+            for a, b in zip(first, ys):
+                assert torch.equal(a, b), rep
+    for g in groups:
+        ref = torch.full_like(g["Y"], float("nan"))
+        mats = [g[k] for k in "ABC"[:g["dim"]]]
+        fn = kron.kron2d_batched_f32 if g["dim"] == 2 else kron.kron3d_batched_f32
+        fn(g["n"], *mats, g["X"], ref, g["count"])
+        torch.cuda.synchronize()
+        assert torch.equal(ref, g["Y"]), (g["dim"], g["n"])
