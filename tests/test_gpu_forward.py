@@ -293,3 +293,40 @@ def test_launch_variants_agree(mode, dim, n):
                     refs[order] = got
     finally:
         kron.kron_set_launch(mcode, dim, n, -1, 0)
+
+
+@pytest.mark.parametrize("n", [2, 5, 10])
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("mode", ["f32", "bf16x3"])
+def test_nan_isolation_in_both_staged_pipelines(mode, dim, n):
+    """The NaN rule holds in both LDS-staged pipelines whatever the launch
+    table picks: the single-slice one (2-D variant 3, 3-D variant 8) and the
+    one with two slices and deferred stores (2-D 4, 3-D 11), which writes a
+    tile's results out only after the next tile's operands are in LDS."""
+    _need_gpu()
+    import paper_1304_7054_amd as kron
+    mcode = {"f32": kron.MODE_F32, "bf16x3": kron.MODE_BF16X3}[mode]
+    # several tiles (2-D: spans of up to 8 tiles) per wavefront at one
+    # workgroup per CU on 256 CUs, plus a ragged tail
+    per_tile = (16 // n) ** dim
+    batch = 1024 * 3 * per_tile * (8 if dim == 2 else 1) + max(1, per_tile // 3)
+    mats, X = _inputs(dim, n, batch, 57, mode)
+    q = batch // 3
+    X = X.copy()
+    X[q * n ** dim + (n ** dim) // 3] = np.nan
+    exact_in = gu.rounded_inputs(mode, mats + [X])
+    want = _oracle(dim, n, exact_in[:-1], exact_in[-1], batch).reshape(batch, -1)
+    keep = np.arange(batch) != q
+    outs = []
+    try:
+        for variant in ((3, 4) if dim == 2 else (8, 11)):
+            kron.kron_set_launch(mcode, dim, n, 1, variant)  # one workgroup per CU: many tiles per wavefront
+            got = gu.run(mode, dim, n, mats, X, batch).reshape(batch, -1)
+            bad = np.nonzero(~np.all(np.isfinite(got), axis=1))[0].tolist()
+            assert bad == [q], (variant, bad[:8])
+            norm, _ = gu.errors(got[keep], want[keep], batch - 1)
+            assert norm <= gu.TOL[mode], variant
+            outs.append(got)
+    finally:
+        kron.kron_set_launch(mcode, dim, n, -1, 0)
+    assert np.array_equal(outs[0][keep], outs[1][keep])
