@@ -106,10 +106,14 @@ struct Grad3D {
     fC = M::template load_fac<N, false>(C, L, g, 0);
   }
 
-  // Contract the G index of t with factor f (data as MFMA operand B), per slab.
+  // Contract the G index of t with factor f (data as MFMA operand B), per
+  // slab.  A slab whose slot holds no element is zero before and after (its
+  // data, or after swap_rows_slabs the factor row it came from, is zero), so
+  // it is skipped.
   __device__ __forceinline__ void stage(const fac_t& f, acc_t (&t)[16]) const {
 #pragma unroll
-    for (int s = 0; s < 16; ++s) t[s] = M::db(f, t[s]);
+    for (int s = 0; s < 16; ++s)
+      if (slot_live<N>(s)) t[s] = M::template db<Geo<N>::kSteps>(f, t[s]);
   }
 
   // t: rows on (g, r) via drow, slabs s -> slabs = old rows, G slots 4g + s = old slabs
@@ -122,10 +126,12 @@ struct Grad3D {
     for (int o = 0; o < 16; ++o) t[o] = u[o];
   }
 
-  // acc += sum over slabs of dY(L-row, G) * T(G, L-col)
+  // acc += sum over slabs of dY(L-row, G) * T(G, L-col) (slabs that hold no
+  // element are zero on both sides and skipped)
   __device__ __forceinline__ static void contract(const acc_t (&dy)[16], const acc_t (&t)[16], acc_t& acc) {
 #pragma unroll
-    for (int s = 0; s < 16; ++s) acc = mma_data<M>(dy[s], t[s], acc);
+    for (int s = 0; s < 16; ++s)
+      if (slot_live<N>(s)) acc = mma_data<M>(dy[s], t[s], acc);
   }
 
   // one gradient of one tile.  F = 0 (dA), 1 (dB), 2 (dC).
@@ -179,7 +185,7 @@ struct Grad2D {
   __device__ __forceinline__ void tile(const io_t* Xt, const io_t* dYt, int64_t rem, acc_t& acc) const {
     constexpr int lax = F, gax = 1 - F;
     GradLoader<M, N, 2> lx(L, g, lax, gax, 0);
-    acc_t t = M::db(F == 0 ? fB : fA, lx.load(Xt, rem, 0, -1));
+    acc_t t = M::template db<Geo<N>::kSteps>(F == 0 ? fB : fA, lx.load(Xt, rem, 0, -1));
     GradLoader<M, N, 2> ly(L, g, lax, gax, 1);
     acc = mma_data<M>(ly.load(dYt, rem, 0, -1), t, acc);
   }
@@ -238,14 +244,19 @@ struct Grad3DStaged {
     constexpr int ysax = F == 2 ? 1 : 2;
     const LaneSlots<N, 3> lx(L, lax, g, gax, false);
     acc_t t[16];
+    // slabs whose slot holds no element stay zero through every step and are
+    // skipped (as in Grad3D)
 #pragma unroll
-    for (int s = 0; s < 16; ++s) t[s] = M::db(F == 2 ? fB : fC, read<sax>(ldsX, lx, s));
+    for (int s = 0; s < 16; ++s)
+      t[s] = slot_live<N>(s) ? M::template db<Geo<N>::kSteps>(F == 2 ? fB : fC, read<sax>(ldsX, lx, s)) : acc_t{0, 0, 0, 0};
     Grad3D<M, N>::swap_rows_slabs(t);
 #pragma unroll
-    for (int s = 0; s < 16; ++s) t[s] = M::db(F == 0 ? fB : fA, t[s]);
+    for (int s = 0; s < 16; ++s)
+      if (slot_live<N>(s)) t[s] = M::template db<Geo<N>::kSteps>(F == 0 ? fB : fA, t[s]);
     const LaneSlots<N, 3> ly(L, lax, g, ygax, M::drow(0, 1) != 1);
 #pragma unroll
-    for (int s = 0; s < 16; ++s) acc = mma_data<M>(read<ysax>(ldsY, ly, s), t[s], acc);
+    for (int s = 0; s < 16; ++s)
+      if (slot_live<N>(s)) acc = mma_data<M>(read<ysax>(ldsY, ly, s), t[s], acc);
   }
 };
 
