@@ -552,22 +552,26 @@ def measure_ex2d_transx(torch, steps, warmup):
             "sampled_rel_err": float(np.sqrt(num / den))}
 
 
-def measure_strided(torch, steps, warmup, ld=17):
+def measure_strided(torch, steps, warmup, ld=17, ldy=None):
     """3-D n=16 FP32 through the strided entry point on padded storage:
-    columns of ld elements (ldx = ldy = ld, ldx2 = ld*16, ldxp = ld*256),
-    beta = 0; ld = 17 takes the element-wise path, ld = 20 the 16-byte
-    vectors.  Algorithmic bytes count the elements addressed (2 GiB)."""
+    columns of ld elements in X (ldx = ld, ldx2 = ld*16, ldxp = ld*256) and
+    of ldy (default ld) in Y, beta = 0.  ld = 17 takes the element-wise
+    path; strides that are multiples of 4 take the 16-byte vectors.  The
+    cases with only X or only Y padded show which side limits the rate.
+    Algorithmic bytes count the elements addressed (2 GiB)."""
     import paper_1304_7054_amd as kron
     import workloads
+    ldy = ld if ldy is None else ldy
     n, batch = 16, workloads.BATCH_3D[16]
     ld2, ldp = ld * n, ld * n * n
+    ldy2, ldyp = ldy * n, ldy * n * n
     g = torch.Generator(device="cuda").manual_seed(workloads.SEED_BASE + 7)
     mats = [torch.rand(n * n, generator=g, device="cuda") * 2 - 1 for _ in range(3)]
     X = torch.randn(ldp * batch, generator=g, device="cuda")
-    Y = torch.empty_like(X)
+    Y = torch.empty(ldyp * batch, device="cuda")
     ws = torch.empty(kron.kron_ex_workspace_size(3, n, kron.MODE_F32), dtype=torch.uint8, device="cuda")
     fn = lambda stream=None: kron.kron3d_batched_strided_f32(n, "N", "N", "N", 1.0, mats[0], n, mats[1], n, mats[2],
-                                                             n, X, ld, ld2, ldp, 0.0, Y, ld, ld2, ldp, batch, ws,
+                                                             n, X, ld, ld2, ldp, 0.0, Y, ldy, ldy2, ldyp, batch, ws,
                                                              stream)
     wall, kmean, kmin = time_launches(torch, fn, (), max(10, steps // 2), warmup)
     torch.cuda.synchronize()
@@ -576,17 +580,19 @@ def measure_strided(torch, steps, warmup, ld=17):
     hm = [m.double().cpu().numpy() for m in mats]
     r = np.arange(n)
     sub = (r[None, None, :] + ld * r[None, :, None] + ld2 * r[:, None, None]).reshape(-1)
+    suby = (r[None, None, :] + ldy * r[None, :, None] + ldy2 * r[:, None, None]).reshape(-1)
     num = den = 0.0
     for q in rng.integers(0, batch, 16):
         x = X[q * ldp:(q + 1) * ldp].double().cpu().numpy()[sub]
         want = oracle.kron3d(n, *hm, x, 1)
-        got = Y[q * ldp:(q + 1) * ldp].double().cpu().numpy()[sub]
+        got = Y[q * ldyp:(q + 1) * ldyp].double().cpu().numpy()[suby]
         num += float(np.sum((got - want) ** 2))
         den += float(np.sum(want ** 2))
     alg = 2 * batch * n ** 3 * 4
     del mats, X, Y, ws
     torch.cuda.empty_cache()
-    return {"mode": f"f32 strided 3-D n=16 (ld {ld}, padded columns, beta=0)", "batch": batch, "ms": round(kmean, 4),
+    lds = f"ld {ld}" if ldy == ld else f"ldx {ld}, ldy {ldy}"
+    return {"mode": f"f32 strided 3-D n=16 ({lds}, padded columns, beta=0)", "batch": batch, "ms": round(kmean, 4),
             "ms_min": round(kmin, 4), "wall_ms_per_step": round(wall, 4),
             "gflops": round(batch * flops_per_op(3, n) / (kmean * 1e-3) / 1e9, 1),
             "gbs": round(alg / (kmean * 1e-3) / 1e9, 1),
@@ -1026,6 +1032,9 @@ def measurement_plan(torch, args):
     plan.append(("ex2d-transx", lambda: measure_ex2d_transx(torch, args.steps, args.warmup)))
     for ld in (17, 20):
         plan.append((f"strided3d-ld{ld}", lambda ld=ld: measure_strided(torch, args.steps, args.warmup, ld)))
+    for ldx, ldy in ((20, 16), (16, 20)):
+        plan.append((f"strided3d-ldx{ldx}-ldy{ldy}",
+                     lambda ldx=ldx, ldy=ldy: measure_strided(torch, args.steps, args.warmup, ldx, ldy)))
     plan.append(("strided2d", lambda: measure_strided2d(torch, args.steps, args.warmup)))
     plan.append(("tkron1", lambda: measure_tkron1(torch, args.steps, args.warmup)))
     plan.append(("backward", lambda: measure_backward(torch, args.steps, args.warmup)))
